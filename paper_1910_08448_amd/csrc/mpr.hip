@@ -1,0 +1,1101 @@
+// mpr.hip -- host runtime of the MPR library (C ABI declared in include/mpr.h) and the
+// kernels around the sweep: validation and data map, sample energy, temperature / window
+// control, averaging finalisation, checkpoint gather and scatter.
+#include "mpr.h"
+#include "mpr_device.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+using namespace mpr;
+
+namespace {
+
+constexpr double kTwoPow32 = 4294967296.0;
+
+// ------------------------------------------------------------------ load-time kernels
+struct GridInfo {
+    int64_t H, W;
+    int64_t site_off;          // packed per-grid site offset
+    uint64_t min_ord, max_ord; // order-preserving images of the sample min / max
+    int64_t n_pred, n_sample;
+    int64_t e_fix;             // sample-bond energy, fixed point 2^-32
+    int64_t n_sample_bonds;
+    int32_t flags;             // 1: mask value > 1, 2: non-finite sample value
+    int32_t pad;
+    double zmin, zmax;
+};
+
+__device__ __forceinline__ uint64_t order_image(double d)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(d);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+double order_inverse(uint64_t o)
+{
+    uint64_t b = (o >> 63) ? (o & 0x7fffffffffffffffull) : ~o;
+    double d;
+    std::memcpy(&d, &b, 8);
+    return d;
+}
+
+template <class T> __device__ __forceinline__ T wave_sum(T v)
+{
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// validation, sample min / max, site counts (one grid per blockIdx.y)
+__global__ __launch_bounds__(256) void k_scan(GridInfo* gi, const double* z, const uint8_t* mask)
+{
+    GridInfo& G = gi[blockIdx.y];
+    const int64_t n = G.H * G.W;
+    uint64_t mn = ~0ull, mx = 0ull;
+    int64_t n_pred = 0, n_samp = 0;
+    int flags = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint8_t m = mask[G.site_off + i];
+        if (m > 1) flags |= 1;
+        else if (m == 1) {
+            const double v = z[G.site_off + i];
+            if (!isfinite(v)) flags |= 2;
+            else {
+                const uint64_t o = order_image(v);
+                mn = o < mn ? o : mn;
+                mx = o > mx ? o : mx;
+                ++n_samp;
+            }
+        } else ++n_pred;
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const uint64_t a = __shfl_xor(mn, off, kWave), b = __shfl_xor(mx, off, kWave);
+        mn = a < mn ? a : mn;
+        mx = b > mx ? b : mx;
+        flags |= __shfl_xor(flags, off, kWave);
+    }
+    n_pred = wave_sum(n_pred);
+    n_samp = wave_sum(n_samp);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        atomicMin((unsigned long long*)&G.min_ord, (unsigned long long)mn);
+        atomicMax((unsigned long long*)&G.max_ord, (unsigned long long)mx);
+        atomicAdd((unsigned long long*)&G.n_pred, (unsigned long long)n_pred);
+        atomicAdd((unsigned long long*)&G.n_sample, (unsigned long long)n_samp);
+        if (flags) atomicOr(&G.flags, flags);
+    }
+}
+
+// sample energy: sum over bonds with both ends sampled of cos[2 pi q (u_i - u_j)], FP64 terms,
+// exact fixed-point accumulation (quantum 2^-32) so the result is independent of the launch
+__global__ __launch_bounds__(256) void k_sample_energy(GridInfo* gi, const double* z,
+                                                       const uint8_t* mask, double q, int periodic)
+{
+    GridInfo& G = gi[blockIdx.y];
+    const int64_t H = G.H, W = G.W, n = H * W;
+    const double lo = G.zmin, inv = 1.0 / (G.zmax - G.zmin);
+    int64_t e = 0, cnt = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (mask[G.site_off + i] != 1) continue;
+        const int64_t y = i / W, x = i - y * W;
+        const double ui = (z[G.site_off + i] - lo) * inv;
+        int64_t nb[2];
+        nb[0] = (x + 1 < W) ? i + 1 : (periodic ? y * W : -1);
+        nb[1] = (y + 1 < H) ? i + W : (periodic ? x : -1);
+        for (int k = 0; k < 2; ++k) {
+            if (nb[k] < 0 || mask[G.site_off + nb[k]] != 1) continue;
+            const double uj = (z[G.site_off + nb[k]] - lo) * inv;
+            e += fixed32(cospi(2.0 * q * (ui - uj)));
+            ++cnt;
+        }
+    }
+    e = wave_sum(e);
+    cnt = wave_sum(cnt);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        atomicAdd((unsigned long long*)&G.e_fix, (unsigned long long)e);
+        atomicAdd((unsigned long long*)&G.n_sample_bonds, (unsigned long long)cnt);
+    }
+}
+
+// plane element -> raw stored value at load: samples get their mapped angle with the sign bit,
+// prediction sites a uniform angle from the (tag 1, sweep 0) Philox counter
+template <class S>
+__global__ __launch_bounds__(256) void k_map_init(const GcDesc* gcs, const GridInfo* gi,
+                                                  const double* z, const uint8_t* mask,
+                                                  void* st0, void* st1, double* acc,
+                                                  uint32_t key0, uint32_t key1)
+{
+    using St = Store<S>;
+    const GcDesc g = gcs[blockIdx.y];
+    const GridInfo& G = gi[g.grid];
+    const int64_t per_plane = (int64_t)g.H * g.pitch;
+    const double lo = G.zmin, inv = 1.0 / (G.zmax - G.zmin);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < 2 * per_plane;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e / per_plane);
+        const int64_t r = e - c * per_plane;
+        const int y = (int)(r / g.pitch);
+        const int k = (int)(r - (int64_t)y * g.pitch);
+        const int x = 2 * k + ((y + c) & 1);
+        typename St::raw v = 0;
+        if (x < g.W) {
+            const int64_t i = (int64_t)y * g.W + x;
+            if (mask[g.grid_site_off + i]) {
+                const double u = (z[g.grid_site_off + i] - lo) * inv;
+                v = St::template encode<double>(u);
+                v |= (typename St::raw)1 << (8 * sizeof(typename St::raw) - 1);
+            } else {
+                const U4 w = philox10(U4{(uint32_t)(y * g.np + (k >> 1)), 0u,
+                                         (uint32_t)g.chain_word, (1u << 1) | (uint32_t)c},
+                                      key0, key1);
+                const uint32_t wa = (k & 1) ? w.z : w.x;
+                v = St::template encode<double>(((double)wa + 0.5) * (1.0 / kTwoPow32));
+            }
+        }
+        ((typename St::raw*)st0)[g.plane_off + e] = v;
+        ((typename St::raw*)st1)[g.plane_off + e] = v;
+        acc[g.plane_off + e] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_copy_z(const GridInfo* gi, const double* z, double* zcopy)
+{
+    const GridInfo& G = gi[blockIdx.y];
+    const int64_t n = G.H * G.W;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        zcopy[G.site_off + i] = z[G.site_off + i];
+}
+
+// ------------------------------------------------------------------ control kernels
+__global__ void k_infer_begin(GcCtl* ctl, int n_gc, double J, double T_min, double T_max,
+                              RunCtl* run, int64_t s_half, int64_t trace_base, int64_t trace_cap)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) { run->s_half = s_half; run->trace_base = trace_base; run->trace_cap = trace_cap; }
+    if (i >= n_gc) return;
+    GcCtl& c = ctl[i];
+    const double T0 = fmin(fmax(4.0 * (c.e_smp + J), T_min), T_max);
+    c.T0 = T0;
+    c.T = T0;
+    c.T_sum = 0.0;
+    c.T_cnt = 0;
+}
+
+__global__ void k_infer_end(GcCtl* ctl, int n_gc)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_gc) return;
+    GcCtl& c = ctl[i];
+    c.T = c.T_cnt > 0 ? c.T_sum / (double)c.T_cnt : c.T0;
+}
+
+__global__ void k_advance(RunCtl* run, int64_t n) { run->base_sweep += n; }
+__global__ void k_set_base(RunCtl* run, int64_t v) { run->base_sweep = v; }
+
+// one block per (grid, chain): sum the per-item partials in item order, then move T and alpha
+template <bool ESINGLE>
+__global__ __launch_bounds__(256) void k_control(const GcDesc* gcs, GcCtl* ctl, const RunCtl* run,
+                                                 const int64_t* e_part, const int32_t* a_part,
+                                                 double* trace, int32_t sweep_off, double J,
+                                                 double acc_target, double T_min, double T_max)
+{
+    __shared__ int64_t s_e[256];
+    __shared__ float s_f[256];
+    __shared__ int64_t s_a[256];
+    const GcDesc g = gcs[blockIdx.x];
+    int64_t e = 0, na = 0;
+    float ef = 0.0f;
+    for (int i = g.item_begin + threadIdx.x; i < g.item_end; i += blockDim.x) {
+        if (ESINGLE) ef += __uint_as_float((uint32_t)e_part[i]);
+        else e += e_part[i];
+        na += a_part[i];
+    }
+    s_e[threadIdx.x] = e;
+    s_f[threadIdx.x] = ef;
+    s_a[threadIdx.x] = na;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s_e[threadIdx.x] += s_e[threadIdx.x + w];
+            s_f[threadIdx.x] += s_f[threadIdx.x + w];
+            s_a[threadIdx.x] += s_a[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    GcCtl& c = ctl[blockIdx.x];
+    const int64_t s = run->base_sweep + sweep_off;
+    double e_sim, r;
+    const double A = g.n_pred > 0 ? (double)s_a[0] / (double)g.n_pred : acc_target;
+    if (ESINGLE) {
+        const float es = -(float)J * s_f[0] / (float)g.n_bonds;
+        const float num = (float)c.e_smp + (float)J, den = es + (float)J;
+        float rf = den <= 1e-30f ? 2.0f : num / den;
+        r = (double)rf;
+        e_sim = (double)es;
+    } else {
+        e_sim = -J * ((double)s_e[0] * (1.0 / kTwoPow32)) / (double)g.n_bonds;
+        const double num = c.e_smp + J, den = e_sim + J;
+        r = den <= 1e-300 ? 2.0 : num / den;
+    }
+    const int64_t t = s - run->trace_base;
+    if (t >= 0 && t < run->trace_cap) {
+        double* tr = trace + ((int64_t)blockIdx.x * run->trace_cap + t) * 4;
+        tr[0] = e_sim; tr[1] = c.T; tr[2] = c.alpha; tr[3] = A;
+    }
+    if (s >= run->s_half) { c.T_sum += c.T; c.T_cnt += 1; }
+    r = fmin(fmax(r, 0.5), 2.0);
+    c.T = fmin(fmax(c.T * r, T_min), T_max);
+    c.alpha = fmin(fmax(c.alpha * A / acc_target, 1e-3), 1.0);
+    c.e_sim = e_sim;
+    c.acc_rate = A;
+}
+
+// ------------------------------------------------------------------ finalise / checkpoint
+template <class S>
+__global__ __launch_bounds__(256) void k_finalize(const GcDesc* gcs, const GridInfo* gi,
+                                                  const void* st, const double* acc,
+                                                  const double* zcopy, double* zhat,
+                                                  int n_chains, int64_t n_avg)
+{
+    using St = Store<S>;
+    const int grid = blockIdx.y;
+    const GridInfo& G = gi[grid];
+    const GcDesc g0 = gcs[grid * n_chains];
+    const int64_t n = G.H * G.W;
+    const int64_t per_plane = (int64_t)g0.H * g0.pitch;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t y = i / G.W, x = i - y * G.W;
+        const int c = (int)((x + y) & 1);
+        const int64_t e = c * per_plane + y * g0.pitch + (x >> 1);
+        const typename St::raw v = ((const typename St::raw*)st)[g0.plane_off + e];
+        double out;
+        if (St::sample(v)) out = zcopy[G.site_off + i];
+        else {
+            double m = 0.0;
+            for (int ch = 0; ch < n_chains; ++ch)
+                m += acc[gcs[grid * n_chains + ch].plane_off + e] / (double)n_avg;
+            m /= (double)n_chains;
+            out = G.zmin + (G.zmax - G.zmin) * m;
+        }
+        zhat[G.site_off + i] = out;
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_get_state(const GcDesc* gcs, const void* st,
+                                                   const double* acc, double* u_out,
+                                                   double* acc_out)
+{
+    using St = Store<S>;
+    const GcDesc g = gcs[blockIdx.y];
+    const int64_t n = (int64_t)g.H * g.W;
+    const int64_t per_plane = (int64_t)g.H * g.pitch;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t y = i / g.W, x = i - y * g.W;
+        const int64_t e = g.plane_off + ((x + y) & 1) * per_plane + y * g.pitch + (x >> 1);
+        if (u_out) u_out[g.site_off + i] = St::template value<double>(((const typename St::raw*)st)[e]);
+        if (acc_out) acc_out[g.site_off + i] = acc[e];
+    }
+}
+
+// check (mode 0) or write (mode 1) prediction-site angles; flag 1 = value outside [0, 1]
+template <class S>
+__global__ __launch_bounds__(256) void k_set_state(const GcDesc* gcs, void* st, double* acc,
+                                                   const double* u_in, const double* acc_in,
+                                                   int* flag, int mode)
+{
+    using St = Store<S>;
+    const GcDesc g = gcs[blockIdx.y];
+    const int64_t n = (int64_t)g.H * g.W;
+    const int64_t per_plane = (int64_t)g.H * g.pitch;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t y = i / g.W, x = i - y * g.W;
+        const int64_t e = g.plane_off + ((x + y) & 1) * per_plane + y * g.pitch + (x >> 1);
+        typename St::raw* p = (typename St::raw*)st + e;
+        if (St::sample(*p)) continue;
+        if (u_in) {
+            const double u = u_in[g.site_off + i];
+            if (mode == 0) {
+                if (!(u >= 0.0 && u <= 1.0)) atomicOr(flag, 1);
+            } else {
+                *p = St::template encode<double>(u);
+            }
+        }
+        if (acc_in && mode == 1) acc[e] = acc_in[g.site_off + i];
+    }
+}
+
+// ------------------------------------------------------------------ sweep kernel table
+using SweepFn = void (*)(SweepArgs);
+
+template <class S, class F> SweepFn pick_sweep(int flags, bool esingle)
+{
+    switch (flags) {
+    case 0: return k_sweep<S, F, 0, false>;
+    case F_ENERGY: return esingle ? k_sweep<S, F, F_ENERGY, true> : k_sweep<S, F, F_ENERGY, false>;
+    case F_ACC: return k_sweep<S, F, F_ACC, false>;
+    default: return k_sweep<S, F, F_DEC, false>;
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+enum { PH_EMPTY = 0, PH_LOADED = 1, PH_TEMPERED = 2, PH_AVERAGED = 3 };
+
+struct mpr_ctx {
+    mpr_config cfg;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool broken = false;
+    std::string err;
+    // shapes
+    int G = 0, C = 1;
+    std::vector<int64_t> H, W, site_off;      // per grid
+    int64_t n_grid_sites = 0;                 // packed per-grid sites
+    std::vector<GcDesc> gcs;
+    std::vector<Item> items;
+    int64_t plane_elems = 0;
+    size_t elem = 8;
+    int sprec = MPR_FP64;
+    bool fsingle = false, esingle = false;
+    // device buffers
+    GcDesc* d_gcs = nullptr;
+    Item* d_items = nullptr;
+    GcCtl* d_ctl = nullptr;
+    RunCtl* d_run = nullptr;
+    RunCtl* d_dbg_run = nullptr;
+    GridInfo* d_gi = nullptr;
+    void* d_state[2] = {nullptr, nullptr};
+    double* d_acc = nullptr;
+    double* d_zcopy = nullptr;
+    int64_t* d_e_part = nullptr;
+    int32_t* d_a_part = nullptr;
+    double* d_trace = nullptr;
+    int* d_flag = nullptr;
+    int64_t trace_cap = 0, trace_len = 0;
+    // host mirrors
+    std::vector<GridInfo> gi;
+    int cur = 0;                 // state buffer holding the current configuration
+    int64_t next_sweep = 0, n_avg = 0;
+    int phase = PH_EMPTY;
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs;   // (mode, cur) -> graph of K sweeps
+    int graph_k = 0;
+    std::vector<int64_t> alloc_sig;                          // shapes the buffers were sized for
+};
+
+static const char* kStatusText[] = {
+    "ok", "invalid argument", "not enough sample data", "periodic grid with an odd side",
+    "call out of order", "out of memory", "HIP runtime error",
+};
+
+static int fail(mpr_ctx* c, int code, const char* fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+        if (code == MPR_EHIP) c->broken = true;
+    }
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? MPR_ENOMEM : MPR_EHIP, "%s: %s",   \
+                        #expr, hipGetErrorString(e_));                                      \
+    } while (0)
+
+static int check_config(const mpr_config* c)
+{
+    if (!c) return MPR_EINVAL;
+    if (!(c->q > 0.0 && c->q <= 0.5)) return MPR_EINVAL;
+    if (!(c->J > 0.0) || !std::isfinite(c->J)) return MPR_EINVAL;
+    if (c->precision < MPR_FP64 || c->precision > MPR_FP16) return MPR_EINVAL;
+    if (c->energy_prec < -1 || c->energy_prec > 1 || c->func_prec < -1 || c->func_prec > 1)
+        return MPR_EINVAL;
+    if (c->precision == MPR_FP16 && c->func_prec == MPR_PREC_DOUBLE) return MPR_EINVAL;
+    if (c->boundary != MPR_OPEN && c->boundary != MPR_PERIODIC) return MPR_EINVAL;
+    if (c->n_chains < 1) return MPR_EINVAL;
+    if (!(c->alpha0 > 0.0 && c->alpha0 <= 1.0)) return MPR_EINVAL;
+    if (!(c->acc_target > 0.0 && c->acc_target < 1.0)) return MPR_EINVAL;
+    if (!(c->T_min > 0.0) || !(c->T_max >= c->T_min) || !std::isfinite(c->T_max)) return MPR_EINVAL;
+    if (c->tile_rows < 0 || c->grid_offset < 0) return MPR_EINVAL;
+    return MPR_OK;
+}
+
+static void free_device(mpr_ctx* c)
+{
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    void* ptrs[] = {c->d_gcs, c->d_items, c->d_ctl, c->d_run, c->d_dbg_run, c->d_gi,
+                    c->d_state[0], c->d_state[1], c->d_acc, c->d_zcopy, c->d_e_part,
+                    c->d_a_part, c->d_trace, c->d_flag};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    c->d_gcs = nullptr; c->d_items = nullptr; c->d_ctl = nullptr; c->d_run = nullptr;
+    c->d_dbg_run = nullptr; c->d_gi = nullptr; c->d_state[0] = c->d_state[1] = nullptr;
+    c->d_acc = nullptr; c->d_zcopy = nullptr; c->d_e_part = nullptr; c->d_a_part = nullptr;
+    c->d_trace = nullptr; c->d_flag = nullptr;
+    c->trace_cap = 0;
+    c->alloc_sig.clear();
+}
+
+// work items: per (grid, chain), row blocks of `rows` rows x strips of 60 lane pairs
+static int choose_rows(const mpr_ctx* c)
+{
+    if (c->cfg.tile_rows > 0) return c->cfg.tile_rows;
+    int64_t base = 0;
+    for (int g = 0; g < c->G; ++g) {
+        const int64_t np = ((c->W[g] + 1) / 2 + 1) / 2;
+        base += c->C * ((np + kOutPairs - 1) / kOutPairs) * c->H[g];
+    }
+    int64_t rows = base / 8192;
+    rows = std::max<int64_t>(16, std::min<int64_t>(256, rows));
+    int r = 16;
+    while (r * 2 <= rows) r *= 2;
+    return r;
+}
+
+static int setup_shapes(mpr_ctx* c, int G, const int64_t* H, const int64_t* W)
+{
+    if (G < 1) return fail(c, MPR_EINVAL, "n_grids must be >= 1");
+    const bool per = c->cfg.boundary == MPR_PERIODIC;
+    for (int g = 0; g < G; ++g) {
+        if (H[g] < 2 || W[g] < 2) return fail(c, MPR_EINVAL, "grid %d: sides must be >= 2", g);
+        if (H[g] > (1 << 30) || W[g] > (1 << 30) || H[g] * W[g] > (int64_t)1 << 40)
+            return fail(c, MPR_EINVAL, "grid %d: too large", g);
+        if (per && ((H[g] & 1) || (W[g] & 1)))
+            return fail(c, MPR_EBIPARTITE, "grid %d: periodic boundary needs even sides", g);
+        if (per && (W[g] % 4))
+            return fail(c, MPR_EINVAL, "grid %d: periodic boundary needs W divisible by 4", g);
+        const int64_t np = ((W[g] + 1) / 2 + 1) / 2;
+        if (H[g] * np >= ((int64_t)1 << 32)) return fail(c, MPR_EINVAL, "grid %d: too large", g);
+    }
+    c->G = G;
+    c->C = c->cfg.n_chains;
+    c->H.assign(H, H + G);
+    c->W.assign(W, W + G);
+    c->site_off.resize(G);
+    int64_t off = 0;
+    for (int g = 0; g < G; ++g) { c->site_off[g] = off; off += H[g] * W[g]; }
+    c->n_grid_sites = off;
+    const int rows = choose_rows(c);
+    c->gcs.clear();
+    c->items.clear();
+    int64_t plane = 0;
+    for (int g = 0; g < G; ++g)
+        for (int ch = 0; ch < c->C; ++ch) {
+            GcDesc d{};
+            d.H = (int32_t)H[g];
+            d.W = (int32_t)W[g];
+            d.wc = (int32_t)((W[g] + 1) / 2);
+            d.np = (d.wc + 1) / 2;
+            d.pitch = ((2 * d.np + 63) / 64) * 64;
+            d.chain_word = (c->cfg.grid_offset + g) * c->C + ch;
+            d.grid = g;
+            d.plane_off = plane;
+            plane += 2 * (int64_t)d.H * d.pitch;
+            d.site_off = (int64_t)(g * c->C + ch) * 0;   // fixed below
+            d.grid_site_off = c->site_off[g];
+            d.n_bonds = per ? 2 * H[g] * W[g] : 2 * H[g] * W[g] - H[g] - W[g];
+            d.item_begin = (int32_t)c->items.size();
+            for (int y0 = 0; y0 < d.H; y0 += rows)
+                for (int p0 = 0; p0 < d.np; p0 += kOutPairs)
+                    c->items.push_back(Item{(int32_t)c->gcs.size(), p0, y0, std::min(d.H, y0 + rows)});
+            d.item_end = (int32_t)c->items.size();
+            c->gcs.push_back(d);
+        }
+    // per-chain packed site offsets: [g][chain][H*W]
+    int64_t so = 0;
+    for (int g = 0; g < G; ++g)
+        for (int ch = 0; ch < c->C; ++ch) { c->gcs[g * c->C + ch].site_off = so; so += H[g] * W[g]; }
+    c->plane_elems = plane;
+    return MPR_OK;
+}
+
+static int alloc_device(mpr_ctx* c)
+{
+    const size_t n_gc = c->gcs.size(), n_items = c->items.size();
+    // a reload with the same shapes reuses every buffer (and the captured graphs)
+    std::vector<int64_t> sig = {(int64_t)n_gc, (int64_t)n_items, c->plane_elems, c->n_grid_sites};
+    for (int g = 0; g < c->G; ++g) { sig.push_back(c->H[g]); sig.push_back(c->W[g]); }
+    if (c->d_gcs && sig == c->alloc_sig) {
+        HIPCHK(c, hipMemcpy(c->d_gcs, c->gcs.data(), n_gc * sizeof(GcDesc), hipMemcpyHostToDevice));
+        RunCtl r{0, 0, 0, 0};
+        HIPCHK(c, hipMemcpy(c->d_run, &r, sizeof r, hipMemcpyHostToDevice));
+        return MPR_OK;
+    }
+    free_device(c);
+    c->alloc_sig = sig;
+    HIPCHK(c, hipMalloc(&c->d_gcs, n_gc * sizeof(GcDesc)));
+    HIPCHK(c, hipMalloc(&c->d_items, n_items * sizeof(Item)));
+    HIPCHK(c, hipMalloc(&c->d_ctl, n_gc * sizeof(GcCtl)));
+    HIPCHK(c, hipMalloc(&c->d_run, sizeof(RunCtl)));
+    HIPCHK(c, hipMalloc(&c->d_dbg_run, sizeof(RunCtl)));
+    HIPCHK(c, hipMalloc(&c->d_gi, c->G * sizeof(GridInfo)));
+    for (int b = 0; b < 2; ++b) HIPCHK(c, hipMalloc(&c->d_state[b], c->plane_elems * c->elem));
+    HIPCHK(c, hipMalloc(&c->d_acc, c->plane_elems * sizeof(double)));
+    HIPCHK(c, hipMalloc(&c->d_zcopy, c->n_grid_sites * sizeof(double)));
+    HIPCHK(c, hipMalloc(&c->d_e_part, n_items * sizeof(int64_t)));
+    HIPCHK(c, hipMalloc(&c->d_a_part, n_items * sizeof(int32_t)));
+    HIPCHK(c, hipMalloc(&c->d_flag, sizeof(int)));
+    HIPCHK(c, hipMemcpy(c->d_gcs, c->gcs.data(), n_gc * sizeof(GcDesc), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_items, c->items.data(), n_items * sizeof(Item), hipMemcpyHostToDevice));
+    RunCtl r{0, 0, 0, 0};
+    HIPCHK(c, hipMemcpy(c->d_run, &r, sizeof r, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_dbg_run, &r, sizeof r, hipMemcpyHostToDevice));
+    return MPR_OK;
+}
+
+static dim3 site_grid(int64_t n, int ys)
+{
+    int64_t b = (n + 255) / 256;
+    b = std::max<int64_t>(1, std::min<int64_t>(b, 4096));
+    return dim3((unsigned)b, (unsigned)ys);
+}
+
+template <class S> static void launch_map(mpr_ctx* c, const double* z, const uint8_t* mask)
+{
+    int64_t maxp = 0;
+    for (auto& g : c->gcs) maxp = std::max<int64_t>(maxp, 2 * (int64_t)g.H * g.pitch);
+    const uint32_t k0 = (uint32_t)(c->cfg.seed & 0xffffffffu), k1 = (uint32_t)(c->cfg.seed >> 32);
+    hipLaunchKernelGGL(k_map_init<S>, site_grid(maxp, (int)c->gcs.size()), dim3(256), 0, c->stream,
+                       c->d_gcs, c->d_gi, z, mask, c->d_state[0], c->d_state[1], c->d_acc,
+                       k0, k1);
+}
+
+template <class S> static void launch_get_state(mpr_ctx* c, double* u, double* acc, dim3 grid)
+{
+    hipLaunchKernelGGL(k_get_state<S>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_state[c->cur], c->d_acc, u, acc);
+}
+template <class S> static void launch_set_state(mpr_ctx* c, const double* u, const double* acc, int mode, dim3 grid)
+{
+    hipLaunchKernelGGL(k_set_state<S>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_state[c->cur], c->d_acc, u, acc, c->d_flag, mode);
+}
+
+extern "C" {
+
+void mpr_config_default(mpr_config* cfg)
+{
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof *cfg);
+    cfg->q = 0.5;
+    cfg->J = 1.0;
+    cfg->precision = MPR_FP64;
+    cfg->energy_prec = MPR_PREC_DEFAULT;
+    cfg->func_prec = MPR_PREC_DEFAULT;
+    cfg->boundary = MPR_OPEN;
+    cfg->n_chains = 1;
+    cfg->seed = 1;
+    cfg->alpha0 = 1.0;
+    cfg->acc_target = 0.3;
+    cfg->T_min = 1e-6;
+    cfg->T_max = 10.0;
+}
+
+const char* mpr_strerror(int s)
+{
+    if (s < 0 || s > MPR_EHIP) return "unknown status";
+    return kStatusText[s];
+}
+
+const char* mpr_last_error(mpr_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+static int create_common(const mpr_config* cfg, void* stream, mpr_ctx** out)
+{
+    if (!out) return MPR_EINVAL;
+    *out = nullptr;
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    mpr_ctx* c = new (std::nothrow) mpr_ctx();
+    if (!c) return MPR_ENOMEM;
+    c->cfg = *cfg;
+    c->stream = (hipStream_t)stream;
+    c->sprec = cfg->precision;
+    c->elem = cfg->precision == MPR_FP64 ? 8 : (cfg->precision == MPR_FP32 ? 4 : 2);
+    c->fsingle = cfg->func_prec == MPR_PREC_DEFAULT ? cfg->precision != MPR_FP64
+                                                    : cfg->func_prec == MPR_PREC_SINGLE;
+    c->esingle = cfg->energy_prec == MPR_PREC_SINGLE;
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return MPR_EHIP; }
+    c->graph_k = cfg->graph_sweeps == 0 ? 32 : cfg->graph_sweeps;
+    if (c->graph_k > 0 && (c->graph_k & 1)) c->graph_k += 1;
+    if (!c->stream) c->graph_k = -1;   // the legacy default stream cannot be captured
+    *out = c;
+    return MPR_OK;
+}
+
+int mpr_create(const mpr_config* cfg, void* stream, mpr_ctx** out)
+{
+    return create_common(cfg, stream, out);
+}
+
+int mpr_batch_create(const mpr_config* cfg, void* stream, int32_t n_grids, const int64_t* H,
+                     const int64_t* W, mpr_ctx** out)
+{
+    if (!H || !W || n_grids < 1) return MPR_EINVAL;
+    int rc = create_common(cfg, stream, out);
+    if (rc) return rc;
+    rc = setup_shapes(*out, n_grids, H, W);
+    if (rc) { delete *out; *out = nullptr; }
+    return rc;
+}
+
+void mpr_destroy(mpr_ctx* c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    free_device(c);
+    delete c;
+}
+
+static int usable(mpr_ctx* c)
+{
+    if (!c) return MPR_EINVAL;
+    if (c->broken) return fail(c, MPR_EHIP, "context is unusable after an earlier HIP error");
+    return MPR_OK;
+}
+
+static int load_common(mpr_ctx* c, const double* z, const uint8_t* mask)
+{
+    int rc = alloc_device(c);
+    if (rc) return rc;
+    c->gi.assign(c->G, GridInfo{});
+    int64_t max_sites = 0;
+    for (int g = 0; g < c->G; ++g) {
+        GridInfo& G = c->gi[g];
+        G.H = c->H[g]; G.W = c->W[g]; G.site_off = c->site_off[g];
+        G.min_ord = ~0ull; G.max_ord = 0;
+        max_sites = std::max(max_sites, G.H * G.W);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_gi, c->gi.data(), c->G * sizeof(GridInfo), hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_scan, site_grid(max_sites, c->G), dim3(256), 0, c->stream, c->d_gi, z, mask);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->gi.data(), c->d_gi, c->G * sizeof(GridInfo), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int g = 0; g < c->G; ++g) {
+        GridInfo& G = c->gi[g];
+        if (G.flags & 1) return fail(c, MPR_EINVAL, "grid %d: mask values must be 0 or 1", g);
+        if (G.flags & 2) return fail(c, MPR_EINVAL, "grid %d: non-finite value at a sample site", g);
+        if (G.n_sample < 1) return fail(c, MPR_ENOSAMPLE, "grid %d: no sample site", g);
+        G.zmin = order_inverse(G.min_ord);
+        G.zmax = order_inverse(G.max_ord);
+        if (!(G.zmax > G.zmin)) return fail(c, MPR_ENOSAMPLE, "grid %d: all sample values are equal", g);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_gi, c->gi.data(), c->G * sizeof(GridInfo), hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_sample_energy, site_grid(max_sites, c->G), dim3(256), 0, c->stream, c->d_gi,
+                       z, mask, c->cfg.q, (int)(c->cfg.boundary == MPR_PERIODIC));
+    hipLaunchKernelGGL(k_copy_z, site_grid(max_sites, c->G), dim3(256), 0, c->stream, c->d_gi, z, c->d_zcopy);
+    switch (c->sprec) {
+    case MPR_FP64: launch_map<double>(c, z, mask); break;
+    case MPR_FP32: launch_map<float>(c, z, mask); break;
+    default: launch_map<_Float16>(c, z, mask); break;
+    }
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->gi.data(), c->d_gi, c->G * sizeof(GridInfo), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<GcCtl> ctl(c->gcs.size());
+    for (size_t i = 0; i < c->gcs.size(); ++i) {
+        GcDesc& d = c->gcs[i];
+        const GridInfo& G = c->gi[d.grid];
+        if (G.n_sample_bonds == 0)
+            return fail(c, MPR_ENOSAMPLE, "grid %d: no bond joins two sample sites", d.grid);
+        d.n_pred = G.n_pred;
+        GcCtl& k = ctl[i];
+        std::memset(&k, 0, sizeof k);
+        k.alpha = c->cfg.alpha0;
+        k.e_smp = -c->cfg.J * ((double)G.e_fix / kTwoPow32) / (double)G.n_sample_bonds;
+    }
+    HIPCHK(c, hipMemcpy(c->d_gcs, c->gcs.data(), c->gcs.size() * sizeof(GcDesc), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_ctl, ctl.data(), ctl.size() * sizeof(GcCtl), hipMemcpyHostToDevice));
+    c->cur = 0;
+    c->next_sweep = 0;
+    c->n_avg = 0;
+    c->trace_len = 0;
+    c->phase = PH_LOADED;
+    return MPR_OK;
+}
+
+int mpr_load(mpr_ctx* c, int64_t H, int64_t W, const double* z, const uint8_t* mask)
+{
+    int rc = usable(c);
+    if (rc) return rc;
+    if (!z || !mask) return fail(c, MPR_EINVAL, "null data pointer");
+    if (c->G > 1) return fail(c, MPR_EINVAL, "batched context: use mpr_batch_load");
+    rc = setup_shapes(c, 1, &H, &W);
+    if (rc) { c->phase = PH_EMPTY; return rc; }
+    rc = load_common(c, z, mask);
+    if (rc) c->phase = PH_EMPTY;
+    return rc;
+}
+
+int mpr_batch_load(mpr_ctx* c, const double* z, const uint8_t* mask)
+{
+    int rc = usable(c);
+    if (rc) return rc;
+    if (!z || !mask) return fail(c, MPR_EINVAL, "null data pointer");
+    if (c->G < 1) return fail(c, MPR_ESTATE, "no grid shapes: use mpr_load or mpr_batch_create");
+    rc = load_common(c, z, mask);
+    if (rc) c->phase = PH_EMPTY;
+    return rc;
+}
+
+// ------------------------------------------------------------------ sweep launches
+enum { MODE_EQUIL = 0, MODE_AVG = 1, MODE_BURN = 2 };
+
+static SweepFn sweep_fn(const mpr_ctx* c, int flags)
+{
+    switch (c->sprec) {
+    case MPR_FP64: return c->fsingle ? pick_sweep<double, float>(flags, c->esingle)
+                                     : pick_sweep<double, double>(flags, c->esingle);
+    case MPR_FP32: return c->fsingle ? pick_sweep<float, float>(flags, c->esingle)
+                                     : pick_sweep<float, double>(flags, c->esingle);
+    default: return pick_sweep<_Float16, float>(flags, c->esingle);
+    }
+}
+
+static void enqueue_sweep(mpr_ctx* c, int flags, int sweep_off, int src_buf, const RunCtl* run,
+                          uint8_t* dec)
+{
+    SweepArgs a{};
+    a.items = c->d_items;
+    a.gcs = c->d_gcs;
+    a.ctl = c->d_ctl;
+    a.run = run;
+    a.src = c->d_state[src_buf];
+    a.dst = c->d_state[1 - src_buf];
+    a.acc = c->d_acc;
+    a.dec = dec;
+    a.e_part = c->d_e_part;
+    a.a_part = c->d_a_part;
+    a.n_items = (int32_t)c->items.size();
+    a.sweep_off = sweep_off;
+    a.key0 = (uint32_t)(c->cfg.seed & 0xffffffffu);
+    a.key1 = (uint32_t)(c->cfg.seed >> 32);
+    a.q = c->cfg.q;
+    a.J = c->cfg.J;
+    a.periodic = c->cfg.boundary == MPR_PERIODIC;
+    const unsigned blocks = (unsigned)((c->items.size() + kWavesPerBlock - 1) / kWavesPerBlock);
+    SweepFn fn = sweep_fn(c, flags);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(kWave * kWavesPerBlock), 0, c->stream, a);
+}
+
+static void enqueue_control(mpr_ctx* c, int sweep_off)
+{
+    auto fn = c->esingle ? k_control<true> : k_control<false>;
+    hipLaunchKernelGGL(fn, dim3((unsigned)c->gcs.size()), dim3(256), 0, c->stream, c->d_gcs, c->d_ctl,
+                       c->d_run, c->d_e_part, c->d_a_part, c->d_trace, sweep_off, c->cfg.J,
+                       c->cfg.acc_target, c->cfg.T_min, c->cfg.T_max);
+}
+
+// n sweeps of `mode` starting from buffer c->cur; sweep i reads buffer (cur + i) & 1
+static void enqueue_block(mpr_ctx* c, int mode, int n)
+{
+    const int flags = mode == MODE_EQUIL ? F_ENERGY : (mode == MODE_AVG ? F_ACC : 0);
+    int buf = c->cur;
+    for (int i = 0; i < n; ++i) {
+        enqueue_sweep(c, flags, i, buf, c->d_run, nullptr);
+        if (mode == MODE_EQUIL) enqueue_control(c, i);
+        buf ^= 1;
+    }
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, c->stream, c->d_run, (int64_t)n);
+}
+
+static int run_sweeps(mpr_ctx* c, int mode, int n)
+{
+    int done = 0;
+    const int K = c->graph_k;
+    if (K > 0 && n >= K) {
+        auto key = std::make_pair(mode, c->cur);
+        hipGraphExec_t exec = nullptr;
+        auto it = c->graphs.find(key);
+        if (it == c->graphs.end()) {
+            HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            enqueue_block(c, mode, K);
+            hipGraph_t graph = nullptr;
+            HIPCHK(c, hipStreamEndCapture(c->stream, &graph));
+            HIPCHK(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+            (void)hipGraphDestroy(graph);
+            c->graphs[key] = exec;
+        } else exec = it->second;
+        for (; done + K <= n; done += K) HIPCHK(c, hipGraphLaunch(exec, c->stream));
+        // K is even: the buffer parity is unchanged
+    }
+    if (done < n) {
+        enqueue_block(c, mode, n - done);
+        if ((n - done) & 1) c->cur ^= 1;
+    }
+    HIPCHK(c, hipGetLastError());
+    c->next_sweep += n;
+    return MPR_OK;
+}
+
+int mpr_infer_temperature(mpr_ctx* c, int32_t n_equil, double* T_host)
+{
+    int rc = usable(c);
+    if (rc) return rc;
+    if (c->phase < PH_LOADED) return fail(c, MPR_ESTATE, "no data loaded");
+    if (n_equil < 0) return fail(c, MPR_EINVAL, "n_equil < 0");
+    const int n_gc = (int)c->gcs.size();
+    if (n_equil > c->trace_cap) {
+        if (c->d_trace) (void)hipFree(c->d_trace);
+        c->d_trace = nullptr;
+        HIPCHK(c, hipMalloc(&c->d_trace, (size_t)n_gc * std::max(n_equil, 1) * 4 * sizeof(double)));
+        c->trace_cap = n_equil;
+        for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);   // captured trace pointer
+        c->graphs.clear();
+    }
+    hipLaunchKernelGGL(k_infer_begin, dim3((n_gc + 255) / 256), dim3(256), 0, c->stream, c->d_ctl,
+                       n_gc, c->cfg.J, c->cfg.T_min, c->cfg.T_max, c->d_run,
+                       (int64_t)(c->next_sweep + n_equil / 2), (int64_t)c->next_sweep,
+                       (int64_t)c->trace_cap);
+    rc = run_sweeps(c, MODE_EQUIL, n_equil);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_infer_end, dim3((n_gc + 255) / 256), dim3(256), 0, c->stream, c->d_ctl, n_gc);
+    HIPCHK(c, hipGetLastError());
+    c->trace_len = n_equil;
+    c->phase = std::max(c->phase, (int)PH_TEMPERED);
+    if (T_host) {
+        std::vector<GcCtl> ctl(n_gc);
+        HIPCHK(c, hipMemcpyAsync(ctl.data(), c->d_ctl, n_gc * sizeof(GcCtl), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int i = 0; i < n_gc; ++i) T_host[i] = ctl[i].T;
+    }
+    return MPR_OK;
+}
+
+int mpr_set_temperature(mpr_ctx* c, double T)
+{
+    int rc = usable(c);
+    if (rc) return rc;
+    if (c->phase < PH_LOADED) return fail(c, MPR_ESTATE, "no data loaded");
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(c, MPR_EINVAL, "temperature must be > 0");
+    std::vector<GcCtl> ctl(c->gcs.size());
+    HIPCHK(c, hipMemcpyAsync(ctl.data(), c->d_ctl, ctl.size() * sizeof(GcCtl), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto& k : ctl) k.T = T;
+    HIPCHK(c, hipMemcpyAsync(c->d_ctl, ctl.data(), ctl.size() * sizeof(GcCtl), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->phase = std::max(c->phase, (int)PH_TEMPERED);
+    return MPR_OK;
+}
+
+int mpr_burn_in(mpr_ctx* c, int32_t n)
+{
+    int rc = usable(c);
+    if (rc) return rc;
+    if (n < 0) return fail(c, MPR_EINVAL, "n < 0");
+    if (c->phase < PH_TEMPERED) return fail(c, MPR_ESTATE, "no temperature: infer or set it first");
+    return run_sweeps(c, MODE_BURN, n);
+}
+
+int mpr_run(mpr_ctx* c, int32_t n_avg)
+{
+    int rc = usable(c);
+    if (rc) return rc;
+    if (n_avg < 0) return fail(c, MPR_EINVAL, "n_avg < 0");
+    if (c->phase < PH_TEMPERED) return fail(c, MPR_ESTATE, "no temperature: infer or set it first");
+    rc = run_sweeps(c, MODE_AVG, n_avg);
+    if (rc) return rc;
+    c->n_avg += n_avg;
+    if (n_avg > 0) c->phase = PH_AVERAGED;
+    return MPR_OK;
+}
+
+int mpr_get_predictions(mpr_ctx* c, double* zhat)
+{
+    int rc = usable(c);
+    if (rc) return rc;
+    if (!zhat) return fail(c, MPR_EINVAL, "null output");
+    if (c->phase < PH_AVERAGED || c->n_avg == 0) return fail(c, MPR_ESTATE, "no averaging sweep yet");
+    int64_t max_sites = 0;
+    for (int g = 0; g < c->G; ++g) max_sites = std::max(max_sites, c->H[g] * c->W[g]);
+    const dim3 grid = site_grid(max_sites, c->G);
+    switch (c->sprec) {
+    case MPR_FP64: hipLaunchKernelGGL(k_finalize<double>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_gi, c->d_state[c->cur], c->d_acc, c->d_zcopy, zhat, c->C, c->n_avg); break;
+    case MPR_FP32: hipLaunchKernelGGL(k_finalize<float>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_gi, c->d_state[c->cur], c->d_acc, c->d_zcopy, zhat, c->C, c->n_avg); break;
+    default: hipLaunchKernelGGL(k_finalize<_Float16>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_gi, c->d_state[c->cur], c->d_acc, c->d_zcopy, zhat, c->C, c->n_avg); break;
+    }
+    HIPCHK(c, hipGetLastError());
+    return MPR_OK;
+}
+
+int mpr_get_stats(mpr_ctx* c, mpr_chain_stats* out)
+{
+    int rc = usable(c);
+    if (rc) return rc;
+    if (!out) return fail(c, MPR_EINVAL, "null output");
+    if (c->phase < PH_LOADED) return fail(c, MPR_ESTATE, "no data loaded");
+    std::vector<GcCtl> ctl(c->gcs.size());
+    HIPCHK(c, hipMemcpyAsync(ctl.data(), c->d_ctl, ctl.size() * sizeof(GcCtl), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < ctl.size(); ++i) {
+        const GcDesc& d = c->gcs[i];
+        const GridInfo& G = c->gi[d.grid];
+        mpr_chain_stats& s = out[i];
+        s.T = ctl[i].T; s.alpha = ctl[i].alpha; s.e_sample = ctl[i].e_smp; s.e_sim = ctl[i].e_sim;
+        s.acc_rate = ctl[i].acc_rate; s.n_pred = d.n_pred; s.n_bonds = d.n_bonds;
+        s.n_sample_bonds = G.n_sample_bonds; s.zmin = G.zmin; s.zmax = G.zmax;
+    }
+    return MPR_OK;
+}
+
+int mpr_get_trace(mpr_ctx* c, int32_t gc, int32_t max_entries, double* out, int32_t* n_out)
+{
+    int rc = usable(c);
+    if (rc) return rc;
+    if (!out || gc < 0 || gc >= (int)c->gcs.size() || max_entries < 0)
+        return fail(c, MPR_EINVAL, "bad trace request");
+    const int64_t n = std::min<int64_t>(c->trace_len, max_entries);
+    if (n > 0) {
+        HIPCHK(c, hipMemcpyAsync(out, c->d_trace + (size_t)gc * c->trace_cap * 4, n * 4 * sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    if (n_out) *n_out = (int32_t)n;
+    return MPR_OK;
+}
+
+static dim3 gc_grid(const mpr_ctx* c)
+{
+    int64_t m = 0;
+    for (int g = 0; g < c->G; ++g) m = std::max(m, c->H[g] * c->W[g]);
+    return site_grid(m, (int)c->gcs.size());
+}
+
+int mpr_get_state(mpr_ctx* c, double* u, double* acc, double* ctl_host, int64_t* meta)
+{
+    int rc = usable(c);
+    if (rc) return rc;
+    if (c->phase < PH_LOADED) return fail(c, MPR_ESTATE, "no data loaded");
+    if (u || acc) {
+        switch (c->sprec) {
+        case MPR_FP64: launch_get_state<double>(c, u, acc, gc_grid(c)); break;
+        case MPR_FP32: launch_get_state<float>(c, u, acc, gc_grid(c)); break;
+        default: launch_get_state<_Float16>(c, u, acc, gc_grid(c)); break;
+        }
+        HIPCHK(c, hipGetLastError());
+    }
+    if (ctl_host) {
+        std::vector<GcCtl> ctl(c->gcs.size());
+        HIPCHK(c, hipMemcpyAsync(ctl.data(), c->d_ctl, ctl.size() * sizeof(GcCtl), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (size_t i = 0; i < ctl.size(); ++i) { ctl_host[2 * i] = ctl[i].T; ctl_host[2 * i + 1] = ctl[i].alpha; }
+    }
+    if (meta) { meta[0] = c->next_sweep; meta[1] = c->n_avg; meta[2] = c->phase; }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return MPR_OK;
+}
+
+int mpr_set_state(mpr_ctx* c, const double* u, const double* acc, const double* ctl_host,
+                  const int64_t* meta)
+{
+    int rc = usable(c);
+    if (rc) return rc;
+    if (c->phase < PH_LOADED) return fail(c, MPR_ESTATE, "no data loaded");
+    if (meta && (meta[0] < 0 || meta[1] < 0 || meta[2] < PH_LOADED || meta[2] > PH_AVERAGED))
+        return fail(c, MPR_EINVAL, "bad checkpoint metadata");
+    if (ctl_host)
+        for (size_t i = 0; i < c->gcs.size(); ++i)
+            if (!(ctl_host[2 * i] > 0.0) || !(ctl_host[2 * i + 1] > 0.0 && ctl_host[2 * i + 1] <= 1.0))
+                return fail(c, MPR_EINVAL, "bad temperature or window in checkpoint");
+    if (u) {
+        HIPCHK(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
+        switch (c->sprec) {
+        case MPR_FP64: launch_set_state<double>(c, u, nullptr, 0, gc_grid(c)); break;
+        case MPR_FP32: launch_set_state<float>(c, u, nullptr, 0, gc_grid(c)); break;
+        default: launch_set_state<_Float16>(c, u, nullptr, 0, gc_grid(c)); break;
+        }
+        int flag = 0;
+        HIPCHK(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (flag) return fail(c, MPR_EINVAL, "checkpoint angle outside [0, 1] at a prediction site");
+    }
+    if (u || acc) {
+        switch (c->sprec) {
+        case MPR_FP64: launch_set_state<double>(c, u, acc, 1, gc_grid(c)); break;
+        case MPR_FP32: launch_set_state<float>(c, u, acc, 1, gc_grid(c)); break;
+        default: launch_set_state<_Float16>(c, u, acc, 1, gc_grid(c)); break;
+        }
+        HIPCHK(c, hipGetLastError());
+    }
+    if (ctl_host) {
+        std::vector<GcCtl> ctl(c->gcs.size());
+        HIPCHK(c, hipMemcpyAsync(ctl.data(), c->d_ctl, ctl.size() * sizeof(GcCtl), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (size_t i = 0; i < ctl.size(); ++i) { ctl[i].T = ctl_host[2 * i]; ctl[i].alpha = ctl_host[2 * i + 1]; }
+        HIPCHK(c, hipMemcpyAsync(c->d_ctl, ctl.data(), ctl.size() * sizeof(GcCtl), hipMemcpyHostToDevice, c->stream));
+    }
+    if (meta) {
+        c->next_sweep = meta[0];
+        c->n_avg = meta[1];
+        c->phase = (int)meta[2];
+        hipLaunchKernelGGL(k_set_base, dim3(1), dim3(1), 0, c->stream, c->d_run, (int64_t)c->next_sweep);
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return MPR_OK;
+}
+
+int mpr_debug_sweep(mpr_ctx* c, int32_t sweep, uint8_t* dec)
+{
+    int rc = usable(c);
+    if (rc) return rc;
+    if (!dec || sweep < 0) return fail(c, MPR_EINVAL, "bad debug sweep arguments");
+    if (c->phase < PH_TEMPERED) return fail(c, MPR_ESTATE, "no temperature: infer or set it first");
+    int64_t total = 0;
+    for (int g = 0; g < c->G; ++g) total += c->H[g] * c->W[g] * c->C;
+    HIPCHK(c, hipMemsetAsync(dec, 0, (size_t)total, c->stream));
+    hipLaunchKernelGGL(k_set_base, dim3(1), dim3(1), 0, c->stream, c->d_dbg_run, (int64_t)sweep);
+    enqueue_sweep(c, F_DEC, 0, c->cur, c->d_dbg_run, dec);
+    c->cur ^= 1;
+    HIPCHK(c, hipGetLastError());
+    return MPR_OK;
+}
+
+int mpr_bench_sweeps(mpr_ctx* c, int32_t n)
+{
+    int rc = usable(c);
+    if (rc) return rc;
+    if (n < 0) return fail(c, MPR_EINVAL, "n < 0");
+    if (c->phase < PH_TEMPERED) return fail(c, MPR_ESTATE, "no temperature: infer or set it first");
+    int buf = c->cur;
+    for (int i = 0; i < n; ++i) {
+        enqueue_sweep(c, F_ENERGY, i, buf, c->d_run, nullptr);
+        buf ^= 1;
+    }
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, c->stream, c->d_run, (int64_t)n);
+    c->cur = buf;
+    c->next_sweep += n;
+    HIPCHK(c, hipGetLastError());
+    return MPR_OK;
+}
+
+int mpr_get_shape(mpr_ctx* c, int32_t* n_grids, int32_t* n_chains, int64_t* n_sites)
+{
+    if (!c) return MPR_EINVAL;
+    if (n_grids) *n_grids = c->G;
+    if (n_chains) *n_chains = c->C;
+    if (n_sites) *n_sites = c->n_grid_sites;
+    return MPR_OK;
+}
+
+}  // extern "C"

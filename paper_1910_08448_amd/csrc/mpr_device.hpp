@@ -1,0 +1,495 @@
+// mpr_device.hpp -- device code of the MPR library for gfx950: counter-based RNG, precision
+// traits, the per-site hybrid update and the fused checkerboard sweep kernel.
+//
+// Layout.  A grid H x W is split by colour c = (x + y) & 1 into two planes of H rows; site
+// (y, x) sits in plane c at row y, column k = x >> 1.  Neighbours of a colour-c site (y, k) are
+// the other plane's (y, k + o - 1), (y, k + o), (y - 1, k), (y + 1, k) with o = (y + c) & 1, so a
+// half-sweep is a 4-point stencil on the other plane.  Angles are stored in revolutions
+// u = phi / 2 pi in [0, 1]; the sign bit marks a sample site (its value never changes), so no
+// mask is read on the hot path.  A lane owns a pair of plane columns (2j, 2j + 1): one
+// Philox4x32-10 call gives both sites of a pair their two uniforms.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpr {
+
+// ------------------------------------------------------------------ shared host/device types
+struct GcDesc {            // one (grid, chain)
+    int32_t H, W;          // grid sides
+    int32_t wc;            // sites per plane row, rounded up: (W + 1) / 2
+    int32_t np;            // lane pairs per plane row: (wc + 1) / 2
+    int32_t pitch;         // elements per plane row (even, >= 2 np)
+    int32_t chain_word;    // Philox counter word 2: grid * n_chains + chain
+    int32_t grid;          // grid index
+    int32_t item_begin;    // first work item of this (grid, chain)
+    int32_t item_end;      // one past its last work item
+    int32_t pad0;
+    int64_t plane_off;     // element offset of its planes [2][H][pitch] in the state arrays
+    int64_t site_off;      // offset into packed per-chain site arrays (row-major)
+    int64_t grid_site_off; // offset into packed per-grid site arrays (z, mask, zhat)
+    int64_t n_pred;        // prediction sites of the grid
+    int64_t n_bonds;       // nearest-neighbour bonds of the grid
+};
+
+struct Item {              // one wave's work: 60 output pairs x rows [y0, y1)
+    int32_t gc, pair0, y0, y1;
+};
+
+struct GcCtl {             // per (grid, chain) control state, device resident
+    double T, alpha;
+    double T0, T_sum;
+    double e_smp, e_sim, acc_rate;
+    int64_t T_cnt;
+};
+
+struct RunCtl {            // per context, device resident
+    int64_t base_sweep;    // Philox sweep index of sweep offset 0 of the next graph replay
+    int64_t s_half;        // first sweep whose temperature enters the estimate
+    int64_t trace_base;    // sweep index of trace entry 0
+    int64_t trace_cap;     // trace entries per (grid, chain)
+};
+
+enum { F_ENERGY = 1, F_ACC = 2, F_DEC = 4 };
+enum { DEC_OR = 1, DEC_ACCEPT = 2, DEC_OUTSIDE = 4 };
+
+constexpr int kWave = 64;
+constexpr int kOutPairs = 60;      // output pairs per wave (2 halo lanes on each side)
+constexpr int kWavesPerBlock = 4;
+
+struct SweepArgs {
+    const Item* items;
+    const GcDesc* gcs;
+    const GcCtl* ctl;
+    const RunCtl* run;
+    const void* src;
+    void* dst;
+    double* acc;
+    uint8_t* dec;
+    int64_t* e_part;           // per item: energy partial (fixed point, or float bits)
+    int32_t* a_part;           // per item: accepted moves
+    int32_t n_items;
+    int32_t sweep_off;         // sweep index = run->base_sweep + sweep_off
+    uint32_t key0, key1;
+    double q, J;
+    int32_t periodic;
+    int32_t pad;
+};
+
+// ------------------------------------------------------------------ Philox4x32-10
+// Salmon, Moraes, Dror, Shaw, SC'11.  The key is uniform across a wave, so the key schedule
+// stays in scalar registers; each round is two 32x32->64 multiplies and two xor3.
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        U4 n;
+        n.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+        n.y = (uint32_t)p1;
+        n.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+        n.w = (uint32_t)p0;
+        c = n;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// ------------------------------------------------------------------ compute precision
+// F = float: hardware transcendental instructions (v_sin_f32 / v_cos_f32 take revolutions,
+// v_exp_f32 is 2^x), uniforms with 23 random bits.  F = double: ocml double functions.
+template <class F> struct Math;
+
+template <> struct Math<float> {
+    static __device__ __forceinline__ void sincos_rev(float x, float& s, float& c)
+    {
+        s = __builtin_amdgcn_sinf(x);
+        c = __builtin_amdgcn_cosf(x);
+    }
+    // exp(-dE / T) as 2^(dE * k) with k = -log2(e) / T
+    static __device__ __forceinline__ float boltz(float dE, float k) { return __builtin_amdgcn_exp2f(dE * k); }
+    static __device__ __forceinline__ float uniform(uint32_t w)
+    {
+        return __builtin_fmaf((float)(w >> 9), 1.0f / 8388608.0f, 1.0f / 16777216.0f);
+    }
+    static __device__ __forceinline__ float atan2(float y, float x) { return atan2f(y, x); }
+    static __device__ __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+};
+
+template <> struct Math<double> {
+    static __device__ __forceinline__ void sincos_rev(double x, double& s, double& c)
+    {
+        sincospi(2.0 * x, &s, &c);
+    }
+    static __device__ __forceinline__ double boltz(double dE, double k) { return exp(dE * k); }
+    static __device__ __forceinline__ double uniform(uint32_t w)
+    {
+        return ((double)w + 0.5) * (1.0 / 4294967296.0);
+    }
+    static __device__ __forceinline__ double atan2(double y, double x) { return ::atan2(y, x); }
+    static __device__ __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+};
+
+// ------------------------------------------------------------------ storage precision
+// Raw bit patterns; the sign bit is the sample flag.
+template <class S> struct Store;
+
+template <> struct Store<double> {
+    using raw = uint64_t;
+    struct pair { raw a, b; };
+    static __device__ __forceinline__ pair load(const void* base, int64_t idx)
+    {
+        const ulonglong2 v = *((const ulonglong2*)((const uint64_t*)base + idx));
+        return {v.x, v.y};
+    }
+    static __device__ __forceinline__ void store(void* base, int64_t idx, pair p)
+    {
+        *((ulonglong2*)((uint64_t*)base + idx)) = make_ulonglong2(p.a, p.b);
+    }
+    static __device__ __forceinline__ bool sample(raw r) { return (r >> 63) != 0; }
+    template <class F> static __device__ __forceinline__ F value(raw r)
+    {
+        return (F)__longlong_as_double((long long)(r & 0x7fffffffffffffffull));
+    }
+    template <class F> static __device__ __forceinline__ raw encode(F u) { return (raw)__double_as_longlong((double)u); }
+    // value rounded to storage precision, in compute precision
+    template <class F> static __device__ __forceinline__ F round(F u) { return (F)(double)u; }
+};
+
+template <> struct Store<float> {
+    using raw = uint32_t;
+    struct pair { raw a, b; };
+    static __device__ __forceinline__ pair load(const void* base, int64_t idx)
+    {
+        const uint2 v = *((const uint2*)((const uint32_t*)base + idx));
+        return {v.x, v.y};
+    }
+    static __device__ __forceinline__ void store(void* base, int64_t idx, pair p)
+    {
+        *((uint2*)((uint32_t*)base + idx)) = make_uint2(p.a, p.b);
+    }
+    static __device__ __forceinline__ bool sample(raw r) { return (r >> 31) != 0; }
+    template <class F> static __device__ __forceinline__ F value(raw r)
+    {
+        return (F)__uint_as_float(r & 0x7fffffffu);
+    }
+    template <class F> static __device__ __forceinline__ raw encode(F u) { return __float_as_uint((float)u); }
+    template <class F> static __device__ __forceinline__ F round(F u) { return (F)(float)u; }
+};
+
+template <> struct Store<_Float16> {
+    using raw = uint16_t;
+    struct pair { raw a, b; };
+    static __device__ __forceinline__ pair load(const void* base, int64_t idx)
+    {
+        const uint32_t v = *((const uint32_t*)((const uint16_t*)base + idx));
+        return {(raw)(v & 0xffffu), (raw)(v >> 16)};
+    }
+    static __device__ __forceinline__ void store(void* base, int64_t idx, pair p)
+    {
+        *((uint32_t*)((uint16_t*)base + idx)) = (uint32_t)p.a | ((uint32_t)p.b << 16);
+    }
+    static __device__ __forceinline__ bool sample(raw r) { return (r >> 15) != 0; }
+    template <class F> static __device__ __forceinline__ F value(raw r)
+    {
+        return (F)__builtin_bit_cast(_Float16, (uint16_t)(r & 0x7fffu));
+    }
+    template <class F> static __device__ __forceinline__ raw encode(F u)
+    {
+        return __builtin_bit_cast(uint16_t, (_Float16)(float)u);
+    }
+    template <class F> static __device__ __forceinline__ F round(F u) { return (F)(float)(_Float16)(float)u; }
+};
+
+// ------------------------------------------------------------------ per-site hybrid update
+// Input: current angle u (storage-rounded), local field (C, S) = sum_j (cos, sin)(2 pi q u_j),
+// uniforms.  Output: new angle (storage-rounded), its (cos, sin)(2 pi q u), decision bits.
+// Over-relaxation: the site energy is -J R cos(2 pi q u - psi), psi = atan2(S, C) in [0, pi]
+// (all neighbour angles 2 pi q u_j lie in [0, pi], so S >= 0); the reflection
+// u' = psi / (pi q) - u keeps it and is used when it stays in [0, 1].  Restricted Metropolis:
+// proposal u + alpha (U_a - 1/2), rejected outside [0, 1], accepted iff
+// U_b < exp(-(E(u_p) - E(u)) / T) with E(v) = -J (C cos 2 pi q v + S sin 2 pi q v) evaluated
+// at the storage-rounded proposal.
+template <class S, class F>
+struct SiteOut {
+    F u, c, s;
+    int dec;
+};
+
+template <class S, class F>
+__device__ __forceinline__ SiteOut<S, F> hybrid_update(F u, bool is_free, F C, F Sn, F q,
+                                                      F inv_piq, F J, F kexp, F alpha,
+                                                      uint32_t wa, uint32_t wb)
+{
+    using M = Math<F>;
+    int dec = 0;
+    // over-relaxation
+    const bool has_field = (C != (F)0) | (Sn != (F)0);
+    const F psi = M::atan2(Sn, C);
+    const F ur = M::fma(psi, inv_piq, -u);
+    const bool do_or = is_free & has_field & (ur >= (F)0) & (ur <= (F)1);
+    F uc = do_or ? Store<S>::template round<F>(ur) : u;
+    dec |= do_or ? DEC_OR : 0;
+    F sc, cc;
+    M::sincos_rev(q * uc, sc, cc);
+    // restricted Metropolis
+    const F up_raw = M::fma(alpha, M::uniform(wa) - (F)0.5, uc);
+    const bool inside = is_free & (up_raw >= (F)0) & (up_raw <= (F)1);
+    const F up = Store<S>::template round<F>(inside ? up_raw : uc);
+    F sp, cp;
+    M::sincos_rev(q * up, sp, cp);
+    // dE = E(up) - E(uc) = J [C (cc - cp) + S (sc - sp)]
+    const F dE = J * M::fma(C, cc - cp, Sn * (sc - sp));
+    const bool acc = inside & (M::uniform(wb) < M::boltz(dE, kexp));
+    dec |= inside ? (acc ? DEC_ACCEPT : 0) : (is_free ? DEC_OUTSIDE : 0);
+    SiteOut<S, F> o;
+    o.u = acc ? up : uc;
+    o.c = acc ? cp : cc;
+    o.s = acc ? sp : sc;
+    o.dec = dec;
+    return o;
+}
+
+// exact 64-bit fixed-point image of an energy term (quantum 2^-32, |e| < 2^19)
+__device__ __forceinline__ int64_t fixed32(double e)
+{
+    const double t = __builtin_fma(e, 4294967296.0, 6755399441055744.0);
+    return (int64_t)__double_as_longlong(t) - (int64_t)0x4338000000000000ll;
+}
+
+template <class T> __device__ __forceinline__ T shfl_up1(T v) { return __shfl_up(v, 1, kWave); }
+template <class T> __device__ __forceinline__ T shfl_down1(T v) { return __shfl_down(v, 1, kWave); }
+
+// per-row data of one lane: (cos, sin) of both pair members, zero where the site is absent
+template <class F> struct RowCS { F c0, s0, c1, s1; };
+
+// ------------------------------------------------------------------ fused sweep kernel
+// One wave = one work item: 64 lanes hold pairs pair0-2 .. pair0+61 of one (grid, chain);
+// lanes 2..61 are output lanes.  The wave walks down rows y0-2 .. y1+1 keeping a 3-row window:
+// the old colour-1 (cos, sin) feed the colour-0 update of the middle row, the new colour-0
+// (cos, sin) of three rows feed the colour-1 update one row behind.  Halo lanes and rows
+// repeat their neighbours' colour-0 updates bit for bit (same inputs, same counters), so
+// items never exchange data within a sweep; the sweep reads `src` and writes `dst`.
+template <class S, class F, int FLAGS, bool ESINGLE>
+__global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
+{
+    using St = Store<S>;
+    using M = Math<F>;
+    using raw = typename St::raw;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (wid >= a.n_items) return;                 // whole waves leave together
+    const Item it = a.items[wid];
+    const GcDesc g = a.gcs[it.gc];
+    const GcCtl ctl = a.ctl[it.gc];
+    const int64_t sweep = a.run->base_sweep + a.sweep_off;
+    const bool per = a.periodic != 0;
+
+    const F q = (F)a.q;
+    const F J = (F)a.J;
+    const F inv_piq = (F)(1.0 / (3.14159265358979323846 * a.q));
+    const F alpha = (F)ctl.alpha;
+    // Boltzmann factor exp(-dE/T): float path 2^(dE * (-log2 e / T)), double path exp(dE * (-1/T))
+    const F kexp = (sizeof(F) == 4) ? (F)(-1.4426950408889634 / ctl.T) : (F)(-1.0 / ctl.T);
+
+    const int j = it.pair0 - 2 + lane;
+    const bool in_range = (j >= 0) & (j < g.np);
+    const int jj = per ? (j + 2 * g.np) % g.np : j;      // periodic: W % 4 == 0, so wc is even
+    const bool lane_ok = per | in_range;
+    const bool out_lane = (lane >= 2) & (lane < kWave - 2) & in_range;
+
+    const S* src = (const S*)a.src + g.plane_off;
+    S* dst = (S*)a.dst + g.plane_off;
+    const int64_t plane_sz = (int64_t)g.H * g.pitch;
+
+    auto row_ok = [&](int y) -> bool { return per | ((y >= 0) & (y < g.H)); };
+    auto wrap = [&](int y) -> int { return per ? (y + g.H) % g.H : y; };
+    // member m of this lane at row y in colour c exists?
+    auto exists = [&](int y, int c, int m) -> bool {
+        const int x = 2 * (2 * jj + m) + ((y + c) & 1);
+        return lane_ok & row_ok(y) & (x < g.W);
+    };
+
+    // raw values of both colours for rows in the window
+    typename St::pair v0_cur, v0_next, v1_m1, v1_0, v1_p1;  // colour-0 old rows k, k+1; colour-1 old rows k-1..k+1
+    RowCS<F> w1_m1, w1_0, w1_p1;    // colour-1 old (cos, sin) rows k-1, k, k+1
+    RowCS<F> w0_m2, w0_m1, w0_0;    // colour-0 new (cos, sin) rows k-2, k-1, k
+    typename St::pair n0_m1, n0_0;  // colour-0 new raw, rows k-1, k
+    int d0_m1a = 0, d0_m1b = 0, d0_0a = 0, d0_0b = 0;   // colour-0 decisions, rows k-1, k
+
+    auto load_pair = [&](int c, int y) -> typename St::pair {
+        typename St::pair p = {0, 0};
+        if (lane_ok & row_ok(y)) p = St::load(src, c * plane_sz + (int64_t)wrap(y) * g.pitch + 2 * jj);
+        return p;
+    };
+    auto cs_of = [&](typename St::pair p, int y, int c) -> RowCS<F> {
+        RowCS<F> r = {(F)0, (F)0, (F)0, (F)0};
+        F s, co;
+        M::sincos_rev(q * St::template value<F>(p.a), s, co);
+        if (exists(y, c, 0)) { r.c0 = co; r.s0 = s; }
+        M::sincos_rev(q * St::template value<F>(p.b), s, co);
+        if (exists(y, c, 1)) { r.c1 = co; r.s1 = s; }
+        return r;
+    };
+
+    // local field of both members of colour c at row y from the other colour's (cos, sin) rows
+    auto field = [&](const RowCS<F>& up, const RowCS<F>& mid, const RowCS<F>& dn, int y, int c,
+                     F& C0, F& S0, F& C1, F& S1) {
+        const int o = (y + c) & 1;
+        // horizontal: o == 0 -> member 0 uses (left lane's member 1, own member 0),
+        //                       member 1 uses (own member 0, own member 1);
+        //             o == 1 -> member 0 uses (own 0, own 1), member 1 uses (own 1, right lane's 0)
+        F hc, hs;
+        if (o == 0) { hc = shfl_up1(mid.c1); hs = shfl_up1(mid.s1); }
+        else        { hc = shfl_down1(mid.c0); hs = shfl_down1(mid.s0); }
+        if (o == 0) {
+            C0 = (hc + mid.c0) + (up.c0 + dn.c0);
+            S0 = (hs + mid.s0) + (up.s0 + dn.s0);
+            C1 = (mid.c0 + mid.c1) + (up.c1 + dn.c1);
+            S1 = (mid.s0 + mid.s1) + (up.s1 + dn.s1);
+        } else {
+            C0 = (mid.c0 + mid.c1) + (up.c0 + dn.c0);
+            S0 = (mid.s0 + mid.s1) + (up.s0 + dn.s0);
+            C1 = (mid.c1 + hc) + (up.c1 + dn.c1);
+            S1 = (mid.s1 + hs) + (up.s1 + dn.s1);
+        }
+    };
+
+    // update both members of colour c at row y; returns the new raw pair, the (cos, sin) of
+    // the new values (zero for absent sites), the decisions, and the energy of the row's bonds
+    auto update_row = [&](typename St::pair old, const RowCS<F>& up, const RowCS<F>& mid,
+                          const RowCS<F>& dn, int y, int c, typename St::pair& nw,
+                          RowCS<F>& ncs, int& da, int& db, F& e) {
+        F C0, S0, C1, S1;
+        field(up, mid, dn, y, c, C0, S0, C1, S1);
+        const bool ex0 = exists(y, c, 0), ex1 = exists(y, c, 1);
+        const bool fr0 = ex0 & !St::sample(old.a);
+        const bool fr1 = ex1 & !St::sample(old.b);
+        U4 r = {0u, 0u, 0u, 0u};
+        if (fr0 | fr1)
+            r = philox10(U4{(uint32_t)(wrap(y) * g.np + jj), (uint32_t)sweep,
+                            (uint32_t)g.chain_word, (uint32_t)c},
+                         a.key0, a.key1);
+        const F u0 = St::template value<F>(old.a);
+        const F u1 = St::template value<F>(old.b);
+        const SiteOut<S, F> o0 = hybrid_update<S, F>(u0, fr0, C0, S0, q, inv_piq, J, kexp, alpha, r.x, r.y);
+        const SiteOut<S, F> o1 = hybrid_update<S, F>(u1, fr1, C1, S1, q, inv_piq, J, kexp, alpha, r.z, r.w);
+        nw.a = fr0 ? St::template encode<F>(o0.u) : old.a;
+        nw.b = fr1 ? St::template encode<F>(o1.u) : old.b;
+        ncs.c0 = ex0 ? o0.c : (F)0;
+        ncs.s0 = ex0 ? o0.s : (F)0;
+        ncs.c1 = ex1 ? o1.c : (F)0;
+        ncs.s1 = ex1 ? o1.s : (F)0;
+        da = o0.dec;
+        db = o1.dec;
+        // bonds of this row's colour-c sites, with their final values
+        e = M::fma(ncs.c0, C0, ncs.s0 * S0) + M::fma(ncs.c1, C1, ncs.s1 * S1);
+    };
+
+    int64_t e_fix = 0;      // fixed-point energy sum (double-precision energy)
+    float e_flt = 0.0f;     // single-precision energy sum
+    int n_acc = 0;
+
+    const int ya = it.y0, yb = it.y1;
+    // prologue: old rows ya-2, ya-1 of both colours
+    {
+        typename St::pair a1 = load_pair(1, ya - 2);
+        v1_m1 = a1;                                  // placeholder, shifted below
+        w1_0 = cs_of(a1, ya - 2, 1);
+        v1_0 = a1;
+        typename St::pair b1 = load_pair(1, ya - 1);
+        w1_p1 = cs_of(b1, ya - 1, 1);
+        v1_p1 = b1;
+        v0_next = load_pair(0, ya - 1);
+        w0_m1 = RowCS<F>{(F)0, (F)0, (F)0, (F)0};
+        w0_0 = w0_m1;
+        n0_0 = {0, 0};
+    }
+    // iteration k: load row k+1, colour-0 update of row k, colour-1 update and store of row k-1
+    for (int k = ya - 1; k <= yb; ++k) {
+        // shift the window
+        w1_m1 = w1_0; w1_0 = w1_p1;
+        v1_m1 = v1_0; v1_0 = v1_p1;
+        w0_m2 = w0_m1; w0_m1 = w0_0;
+        n0_m1 = n0_0;
+        d0_m1a = d0_0a; d0_m1b = d0_0b;
+        v0_cur = v0_next;
+        // load row k+1
+        v1_p1 = load_pair(1, k + 1);
+        w1_p1 = cs_of(v1_p1, k + 1, 1);
+        v0_next = load_pair(0, k + 1);
+        // colour-0 update of row k (needs colour-1 old rows k-1, k, k+1)
+        if (row_ok(k)) {
+            F e_unused;
+            update_row(v0_cur, w1_m1, w1_0, w1_p1, k, 0, n0_0, w0_0, d0_0a, d0_0b, e_unused);
+        } else {
+            n0_0 = v0_cur;
+            w0_0 = RowCS<F>{(F)0, (F)0, (F)0, (F)0};
+            d0_0a = d0_0b = 0;
+        }
+        // colour-1 update of row k-1 (needs colour-0 new rows k-2, k-1, k)
+        const int y = k - 1;
+        if (y >= ya) {
+            typename St::pair n1;
+            RowCS<F> cs1;
+            int d1a, d1b;
+            F e;
+            update_row(v1_m1, w0_m2, w0_m1, w0_0, y, 1, n1, cs1, d1a, d1b, e);
+            if (out_lane) {
+                const int64_t r0 = (int64_t)y * g.pitch + 2 * jj;
+                St::store(dst, r0, n0_m1);
+                St::store(dst, plane_sz + r0, n1);
+                const bool f0a = exists(y, 0, 0) & !St::sample(n0_m1.a);
+                const bool f0b = exists(y, 0, 1) & !St::sample(n0_m1.b);
+                const bool f1a = exists(y, 1, 0) & !St::sample(n1.a);
+                const bool f1b = exists(y, 1, 1) & !St::sample(n1.b);
+                n_acc += ((d0_m1a & DEC_ACCEPT) ? 1 : 0) + ((d0_m1b & DEC_ACCEPT) ? 1 : 0) +
+                         ((d1a & DEC_ACCEPT) ? 1 : 0) + ((d1b & DEC_ACCEPT) ? 1 : 0);
+                if (FLAGS & F_ENERGY) {
+                    if (ESINGLE) e_flt += (float)e;
+                    else e_fix += fixed32((double)e);
+                }
+                if (FLAGS & F_ACC) {
+                    double* acc = a.acc + g.plane_off;
+                    double2 p0 = *((double2*)(acc + r0));
+                    double2 p1 = *((double2*)(acc + plane_sz + r0));
+                    if (f0a) p0.x += St::template value<double>(n0_m1.a);
+                    if (f0b) p0.y += St::template value<double>(n0_m1.b);
+                    if (f1a) p1.x += St::template value<double>(n1.a);
+                    if (f1b) p1.y += St::template value<double>(n1.b);
+                    *((double2*)(acc + r0)) = p0;
+                    *((double2*)(acc + plane_sz + r0)) = p1;
+                }
+                if (FLAGS & F_DEC) {
+                    uint8_t* d = a.dec + g.site_off + (int64_t)y * g.W;
+                    const int xb = 4 * jj;
+                    const int o0 = y & 1, o1 = (y + 1) & 1;
+                    if (exists(y, 0, 0)) d[xb + o0] = f0a ? (uint8_t)d0_m1a : 0;
+                    if (exists(y, 0, 1)) d[xb + 2 + o0] = f0b ? (uint8_t)d0_m1b : 0;
+                    if (exists(y, 1, 0)) d[xb + o1] = f1a ? (uint8_t)d1a : 0;
+                    if (exists(y, 1, 1)) d[xb + 2 + o1] = f1b ? (uint8_t)d1b : 0;
+                }
+            }
+        }
+    }
+
+    // wave reductions -> per-item partials (exact integers, or a fixed-order float tree)
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        n_acc += __shfl_xor(n_acc, off, kWave);
+        if (FLAGS & F_ENERGY) {
+            if (ESINGLE) e_flt += __shfl_xor(e_flt, off, kWave);
+            else e_fix += __shfl_xor(e_fix, off, kWave);
+        }
+    }
+    if (lane == 0) {
+        a.a_part[wid] = n_acc;
+        if (FLAGS & F_ENERGY) a.e_part[wid] = ESINGLE ? (int64_t)__float_as_uint(e_flt) : e_fix;
+    }
+}
+
+}  // namespace mpr

@@ -1,0 +1,242 @@
+"""Python binding of libmpr.so (include/mpr.h): argument marshalling only.
+
+Every step of the method runs in the library's HIP kernels; PyTorch provides device memory
+(tensors) and the stream.  The functions below carry the C names; `Context` wraps them for
+convenience.  If the library is missing, importing this module raises: there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmpr.so")
+
+OK, EINVAL, ENOSAMPLE, EBIPARTITE, ESTATE, ENOMEM, EHIP = range(7)
+FP64, FP32, FP16 = 0, 1, 2
+PREC_DEFAULT, PREC_DOUBLE, PREC_SINGLE = -1, 0, 1
+OPEN, PERIODIC = 0, 1
+DEC_OR, DEC_ACCEPT, DEC_OUTSIDE = 1, 2, 4
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libmpr.so is not built (%s); run paper_1910_08448_amd/build.py" % LIB_PATH)
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+class mpr_config(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_double), ("J", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("energy_prec", ctypes.c_int32),
+                ("func_prec", ctypes.c_int32), ("boundary", ctypes.c_int32),
+                ("n_chains", ctypes.c_int32), ("grid_offset", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("alpha0", ctypes.c_double),
+                ("acc_target", ctypes.c_double), ("T_min", ctypes.c_double),
+                ("T_max", ctypes.c_double), ("tile_rows", ctypes.c_int32),
+                ("graph_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+
+
+class mpr_chain_stats(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("e_sample", ctypes.c_double), ("e_sim", ctypes.c_double),
+                ("acc_rate", ctypes.c_double), ("n_pred", ctypes.c_int64),
+                ("n_bonds", ctypes.c_int64), ("n_sample_bonds", ctypes.c_int64),
+                ("zmin", ctypes.c_double), ("zmax", ctypes.c_double)]
+
+
+_vp, _i32, _i64, _d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_SIG = {
+    "mpr_config_default": (None, [_vp]),
+    "mpr_create": (ctypes.c_int, [_vp, _vp, _vp]),
+    "mpr_batch_create": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp]),
+    "mpr_destroy": (None, [_vp]),
+    "mpr_load": (ctypes.c_int, [_vp, _i64, _i64, _vp, _vp]),
+    "mpr_batch_load": (ctypes.c_int, [_vp, _vp, _vp]),
+    "mpr_infer_temperature": (ctypes.c_int, [_vp, _i32, _vp]),
+    "mpr_set_temperature": (ctypes.c_int, [_vp, _d]),
+    "mpr_burn_in": (ctypes.c_int, [_vp, _i32]),
+    "mpr_run": (ctypes.c_int, [_vp, _i32]),
+    "mpr_get_predictions": (ctypes.c_int, [_vp, _vp]),
+    "mpr_get_stats": (ctypes.c_int, [_vp, _vp]),
+    "mpr_get_trace": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp]),
+    "mpr_get_state": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "mpr_set_state": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "mpr_debug_sweep": (ctypes.c_int, [_vp, _i32, _vp]),
+    "mpr_bench_sweeps": (ctypes.c_int, [_vp, _i32]),
+    "mpr_get_shape": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "mpr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "mpr_last_error": (ctypes.c_char_p, [_vp]),
+}
+EXPORTS = tuple(_SIG)
+for _name, (_res, _args) in _SIG.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+    globals()[_name] = _f
+
+
+class MprError(RuntimeError):
+    def __init__(self, code, what, detail=""):
+        super().__init__("%s: %s (%d) %s" % (what, _lib.mpr_strerror(code).decode(), code, detail))
+        self.code = code
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or host pointer of a numpy array); None -> NULL."""
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return ctypes.c_void_p(t.data_ptr())
+    return t.ctypes.data_as(ctypes.c_void_p)
+
+
+def default_config(**kw):
+    cfg = mpr_config()
+    _lib.mpr_config_default(ctypes.byref(cfg))
+    for k, v in kw.items():
+        if not hasattr(cfg, k):
+            raise TypeError("unknown config field %r" % k)
+        setattr(cfg, k, v)
+    return cfg
+
+
+class Context:
+    """One library context on torch's current device.  `stream` is a torch.cuda.Stream (or None
+    for torch's current stream)."""
+
+    def __init__(self, shapes=None, stream=None, **cfg):
+        import torch
+        self.torch = torch
+        self.cfg = default_config(**cfg)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        sp = ctypes.c_void_p(self.stream.cuda_stream)
+        if shapes is None:
+            rc = _lib.mpr_create(ctypes.byref(self.cfg), sp, ctypes.byref(h))
+            self.shapes = None
+        else:
+            Hs = np.ascontiguousarray([s[0] for s in shapes], dtype=np.int64)
+            Ws = np.ascontiguousarray([s[1] for s in shapes], dtype=np.int64)
+            rc = _lib.mpr_batch_create(ctypes.byref(self.cfg), sp, len(shapes), _ptr(Hs), _ptr(Ws),
+                                       ctypes.byref(h))
+            self.shapes = [(int(a), int(b)) for a, b in zip(Hs, Ws)]
+        if rc != OK:
+            raise MprError(rc, "mpr_create")
+        self.h = h
+
+    def _chk(self, rc, what):
+        if rc != OK:
+            raise MprError(rc, what, _lib.mpr_last_error(self.h).decode())
+
+    def _call(self, what, fn, *args):
+        """Stream-ordered call: the library's stream waits for torch's current stream (inputs
+        written there), and torch's current stream then waits for the library (outputs)."""
+        cur = self.torch.cuda.current_stream()
+        other = cur.cuda_stream != self.stream.cuda_stream
+        if other:
+            self.stream.wait_stream(cur)
+        rc = fn(self.h, *args)
+        if other:
+            cur.wait_stream(self.stream)
+        self._chk(rc, what)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.mpr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- verbs
+    @property
+    def n_chains(self):
+        return self.cfg.n_chains
+
+    @property
+    def n_grids(self):
+        return 1 if self.shapes is None else len(self.shapes)
+
+    def n_sites(self):
+        return sum(h * w for h, w in self.shapes)
+
+    def load(self, z, mask):
+        """z: float64 CUDA tensor [H, W]; mask: uint8 CUDA tensor [H, W]."""
+        assert z.is_cuda and z.dtype == self.torch.float64 and z.is_contiguous()
+        assert mask.is_cuda and mask.dtype == self.torch.uint8 and mask.is_contiguous()
+        self._call("mpr_load", _lib.mpr_load, z.shape[0], z.shape[1], _ptr(z), _ptr(mask))
+        self.shapes = [(int(z.shape[0]), int(z.shape[1]))]
+
+    def batch_load(self, z_packed, mask_packed):
+        assert z_packed.is_cuda and z_packed.dtype == self.torch.float64
+        assert mask_packed.is_cuda and mask_packed.dtype == self.torch.uint8
+        assert z_packed.numel() == self.n_sites() == mask_packed.numel()
+        self._call("mpr_batch_load", _lib.mpr_batch_load, _ptr(z_packed), _ptr(mask_packed))
+
+    def infer_temperature(self, n_equil, want_T=True):
+        T = np.zeros(self.n_grids * self.n_chains) if want_T else None
+        self._call("mpr_infer_temperature", _lib.mpr_infer_temperature, n_equil, _ptr(T))
+        return T
+
+    def set_temperature(self, T):
+        self._call("mpr_set_temperature", _lib.mpr_set_temperature, T)
+
+    def burn_in(self, n):
+        self._call("mpr_burn_in", _lib.mpr_burn_in, n)
+
+    def bench_sweeps(self, n):
+        self._call("mpr_bench_sweeps", _lib.mpr_bench_sweeps, n)
+
+    def run(self, n_avg):
+        self._call("mpr_run", _lib.mpr_run, n_avg)
+
+    def predictions(self, out=None):
+        t = self.torch
+        if out is None:
+            out = t.empty(self.n_sites(), dtype=t.float64, device="cuda")
+        self._call("mpr_get_predictions", _lib.mpr_get_predictions, _ptr(out))
+        return out
+
+    def stats(self):
+        arr = (mpr_chain_stats * (self.n_grids * self.n_chains))()
+        self._call("mpr_get_stats", _lib.mpr_get_stats, arr)
+        return [{k: getattr(s, k) for k, _ in mpr_chain_stats._fields_} for s in arr]
+
+    def trace(self, grid_chain=0, max_entries=1 << 20):
+        n_out = ctypes.c_int32()
+        buf = np.zeros((max_entries, 4))
+        self._call("mpr_get_trace", _lib.mpr_get_trace, grid_chain, max_entries, _ptr(buf), ctypes.byref(n_out))
+        return buf[: n_out.value]
+
+    def get_state(self):
+        t = self.torch
+        n = self.n_sites() * self.n_chains
+        u = t.empty(n, dtype=t.float64, device="cuda")
+        acc = t.empty(n, dtype=t.float64, device="cuda")
+        ctl = np.zeros((self.n_grids * self.n_chains, 2))
+        meta = np.zeros(3, dtype=np.int64)
+        self._call("mpr_get_state", _lib.mpr_get_state, _ptr(u), _ptr(acc), _ptr(ctl), _ptr(meta))
+        return {"u": u, "acc": acc, "ctl": ctl, "meta": meta}
+
+    def set_state(self, u=None, acc=None, ctl=None, meta=None):
+        ctl = None if ctl is None else np.ascontiguousarray(ctl, dtype=np.float64)
+        meta = None if meta is None else np.ascontiguousarray(meta, dtype=np.int64)
+        self._call("mpr_set_state", _lib.mpr_set_state, _ptr(u), _ptr(acc), _ptr(ctl), _ptr(meta))
+
+    def debug_sweep(self, sweep):
+        t = self.torch
+        d = t.empty(self.n_sites() * self.n_chains, dtype=t.uint8, device="cuda")
+        self._call("mpr_debug_sweep", _lib.mpr_debug_sweep, sweep, _ptr(d))
+        return d
+
+
+def predict(z, mask, n_equil, n_avg, stream=None, **cfg):
+    """Whole method on one grid (torch CUDA tensors in, float64 CUDA tensor out)."""
+    ctx = Context(stream=stream, **cfg)
+    ctx.load(z, mask)
+    T = ctx.infer_temperature(n_equil)
+    ctx.run(n_avg)
+    out = ctx.predictions().view(z.shape[0], z.shape[1])
+    ctx.close()
+    return out, T

@@ -69,6 +69,15 @@ def gap_mask(H, W, p_missing, gap, seed):
     return mask
 
 
+def random_state(n_chains, mask, seed):
+    """Synthetic spin state in revolutions: uniform on [0, 1] at prediction sites (mask 0),
+    0 at sample sites; shape [n_chains, H, W]."""
+    rng = np.random.default_rng(seed)
+    u = rng.random((n_chains,) + mask.shape)
+    u[:, mask == 1] = 0.0
+    return u
+
+
 # ---------------------------------------------------------------- named workloads
 def workload(name, seed=1, p_missing=None):
     """Returns dict(z, truth, mask, ...) for the named workloads.

@@ -1,0 +1,73 @@
+"""The C-ABI library loads and exports every entry point include/mpr.h declares; host-side
+argument checks work without a GPU (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpr.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpr_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_1910_08448_amd import mpr
+    return mpr
+
+
+def test_every_declared_symbol_is_exported(M):
+    names = _declared()
+    assert len(names) >= 18
+    lib = ctypes.CDLL(M.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(M.EXPORTS) == set(names)
+
+
+def test_config_struct_layout_matches_header(M):
+    text = open(HEADER).read()
+    body = text[text.index("typedef struct mpr_config"):text.index("} mpr_config;")]
+    fields = re.findall(r"\b(?:double|int32_t|uint64_t)\s+([a-zA-Z_0-9, ]+?)(?:\[\d+\])?;", body)
+    flat = [f.strip() for grp in fields for f in grp.split(",")]
+    assert flat == [n for n, _ in M.mpr_config._fields_]
+    assert ctypes.sizeof(M.mpr_config) == 112
+
+
+def test_defaults_and_host_validation(M):
+    cfg = M.default_config()
+    assert (cfg.q, cfg.J, cfg.precision, cfg.boundary, cfg.n_chains) == (0.5, 1.0, M.FP64, M.OPEN, 1)
+    assert (cfg.alpha0, cfg.acc_target, cfg.T_min, cfg.T_max) == (1.0, 0.3, 1e-6, 10.0)
+    h = ctypes.c_void_p()
+    for kw in [dict(q=0.0), dict(q=0.51), dict(J=0.0), dict(n_chains=0), dict(alpha0=1.5),
+               dict(acc_target=0.0), dict(T_min=0.0), dict(T_min=2.0, T_max=1.0),
+               dict(precision=3), dict(func_prec=5), dict(precision=M.FP16, func_prec=M.PREC_DOUBLE),
+               dict(grid_offset=-1), dict(tile_rows=-2)]:
+        bad = M.default_config(**kw)
+        assert M.mpr_create(ctypes.byref(bad), None, ctypes.byref(h)) == M.EINVAL, kw
+    assert M.mpr_create(None, None, ctypes.byref(h)) == M.EINVAL
+    assert M.mpr_strerror(M.ENOSAMPLE) == b"not enough sample data"
+    assert M.mpr_strerror(99) == b"unknown status"
+    good = M.default_config()
+    one = (ctypes.c_int64 * 1)(4)
+    assert M.mpr_batch_create(ctypes.byref(good), None, 0, one, one, ctypes.byref(h)) == M.EINVAL
+
+
+def test_binding_refuses_missing_library(tmp_path):
+    """Without the built library the binding raises at import; there is no fallback path."""
+    import subprocess
+    import sys
+    import shutil
+    pkg = tmp_path / "paper_1910_08448_amd"
+    pkg.mkdir()
+    shutil.copy(os.path.join(ROOT, "paper_1910_08448_amd", "mpr.py"), pkg / "mpr.py")
+    (pkg / "__init__.py").write_text("")
+    r = subprocess.run([sys.executable, "-c", "import paper_1910_08448_amd.mpr"], cwd=tmp_path,
+                       capture_output=True, text=True)
+    assert r.returncode != 0 and "libmpr.so is not built" in r.stderr
