@@ -27,7 +27,7 @@ struct GridInfo {
     int64_t site_off;          // packed per-grid site offset
     uint64_t min_ord, max_ord; // order-preserving images of the sample min / max
     int64_t n_pred, n_sample;
-    int64_t e_fix;             // sample-bond energy, fixed point 2^-32
+    int64_t e_hi, e_lo;        // sample-bond energy, two-word fixed point (2^-32, 2^-64)
     int64_t n_sample_bonds;
     int32_t flags;             // 1: mask value > 1, 2: non-finite sample value
     int32_t pad;
@@ -45,6 +45,14 @@ double order_inverse(uint64_t o)
     double d;
     std::memcpy(&d, &b, 8);
     return d;
+}
+
+// value of a two-word fixed-point sum hi 2^-32 + lo 2^-64 (hi split so no bit is lost)
+__host__ __device__ inline double fix2_value(int64_t hi, int64_t lo)
+{
+    const int64_t hi_top = hi >> 20, hi_bot = hi - (hi_top << 20);
+    return (double)hi_top * 1048576.0 / kTwoPow32 +
+           ((double)hi_bot / kTwoPow32 + (double)lo / (kTwoPow32 * kTwoPow32));
 }
 
 template <class T> __device__ __forceinline__ T wave_sum(T v)
@@ -101,7 +109,7 @@ __global__ __launch_bounds__(256) void k_sample_energy(GridInfo* gi, const doubl
     GridInfo& G = gi[blockIdx.y];
     const int64_t H = G.H, W = G.W, n = H * W;
     const double lo = G.zmin, inv = 1.0 / (G.zmax - G.zmin);
-    int64_t e = 0, cnt = 0;
+    int64_t e_hi = 0, e_lo = 0, cnt = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         if (mask[G.site_off + i] != 1) continue;
@@ -113,14 +121,18 @@ __global__ __launch_bounds__(256) void k_sample_energy(GridInfo* gi, const doubl
         for (int k = 0; k < 2; ++k) {
             if (nb[k] < 0 || mask[G.site_off + nb[k]] != 1) continue;
             const double uj = (z[G.site_off + nb[k]] - lo) * inv;
-            e += fixed32(cospi(2.0 * q * (ui - uj)));
+            const Fix2 f = fixed64x2(cospi(2.0 * q * (ui - uj)));
+            e_hi += f.hi;
+            e_lo += f.lo;
             ++cnt;
         }
     }
-    e = wave_sum(e);
+    e_hi = wave_sum(e_hi);
+    e_lo = wave_sum(e_lo);
     cnt = wave_sum(cnt);
     if ((threadIdx.x & (kWave - 1)) == 0) {
-        atomicAdd((unsigned long long*)&G.e_fix, (unsigned long long)e);
+        atomicAdd((unsigned long long*)&G.e_hi, (unsigned long long)e_hi);
+        atomicAdd((unsigned long long*)&G.e_lo, (unsigned long long)e_lo);
         atomicAdd((unsigned long long*)&G.n_sample_bonds, (unsigned long long)cnt);
     }
 }
@@ -208,24 +220,26 @@ __global__ __launch_bounds__(256) void k_control(const GcDesc* gcs, GcCtl* ctl, 
                                                  double* trace, int32_t sweep_off, double J,
                                                  double acc_target, double T_min, double T_max)
 {
-    __shared__ int64_t s_e[256];
+    __shared__ int64_t s_e[256], s_l[256];
     __shared__ float s_f[256];
     __shared__ int64_t s_a[256];
     const GcDesc g = gcs[blockIdx.x];
-    int64_t e = 0, na = 0;
+    int64_t e = 0, el = 0, na = 0;
     float ef = 0.0f;
     for (int i = g.item_begin + threadIdx.x; i < g.item_end; i += blockDim.x) {
-        if (ESINGLE) ef += __uint_as_float((uint32_t)e_part[i]);
-        else e += e_part[i];
+        if (ESINGLE) ef += __uint_as_float((uint32_t)e_part[2 * i]);
+        else { e += e_part[2 * i]; el += e_part[2 * i + 1]; }
         na += a_part[i];
     }
     s_e[threadIdx.x] = e;
+    s_l[threadIdx.x] = el;
     s_f[threadIdx.x] = ef;
     s_a[threadIdx.x] = na;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
             s_e[threadIdx.x] += s_e[threadIdx.x + w];
+            s_l[threadIdx.x] += s_l[threadIdx.x + w];
             s_f[threadIdx.x] += s_f[threadIdx.x + w];
             s_a[threadIdx.x] += s_a[threadIdx.x + w];
         }
@@ -243,7 +257,7 @@ __global__ __launch_bounds__(256) void k_control(const GcDesc* gcs, GcCtl* ctl, 
         r = (double)rf;
         e_sim = (double)es;
     } else {
-        e_sim = -J * ((double)s_e[0] * (1.0 / kTwoPow32)) / (double)g.n_bonds;
+        e_sim = -J * fix2_value(s_e[0], s_l[0]) / (double)g.n_bonds;
         const double num = c.e_smp + J, den = e_sim + J;
         r = den <= 1e-300 ? 2.0 : num / den;
     }
@@ -341,14 +355,19 @@ __global__ __launch_bounds__(256) void k_set_state(const GcDesc* gcs, void* st, 
 // ------------------------------------------------------------------ sweep kernel table
 using SweepFn = void (*)(SweepArgs);
 
-template <class S, class F> SweepFn pick_sweep(int flags, bool esingle)
+template <class S, class F, bool PER> SweepFn pick_sweep_b(int flags, bool esingle)
 {
     switch (flags) {
-    case 0: return k_sweep<S, F, 0, false>;
-    case F_ENERGY: return esingle ? k_sweep<S, F, F_ENERGY, true> : k_sweep<S, F, F_ENERGY, false>;
-    case F_ACC: return k_sweep<S, F, F_ACC, false>;
-    default: return k_sweep<S, F, F_DEC, false>;
+    case 0: return k_sweep<S, F, 0, false, PER>;
+    case F_ENERGY: return esingle ? k_sweep<S, F, F_ENERGY, true, PER> : k_sweep<S, F, F_ENERGY, false, PER>;
+    case F_ACC: return k_sweep<S, F, F_ACC, false, PER>;
+    default: return k_sweep<S, F, F_DEC, false, PER>;
     }
+}
+
+template <class S, class F> SweepFn pick_sweep(int flags, bool esingle, bool per)
+{
+    return per ? pick_sweep_b<S, F, true>(flags, esingle) : pick_sweep_b<S, F, false>(flags, esingle);
 }
 
 }  // namespace
@@ -468,9 +487,11 @@ static int choose_rows(const mpr_ctx* c)
         const int64_t np = ((c->W[g] + 1) / 2 + 1) / 2;
         base += c->C * ((np + kOutPairs - 1) / kOutPairs) * c->H[g];
     }
-    int64_t rows = base / 8192;
-    rows = std::max<int64_t>(16, std::min<int64_t>(256, rows));
-    int r = 16;
+    // aim at >= 4096 waves (4 per SIMD of the 1024 SIMDs) while keeping the 4 halo rows of an
+    // item small against its rows
+    int64_t rows = base / 4096;
+    rows = std::max<int64_t>(4, std::min<int64_t>(128, rows));
+    int r = 4;
     while (r * 2 <= rows) r *= 2;
     return r;
 }
@@ -488,7 +509,9 @@ static int setup_shapes(mpr_ctx* c, int G, const int64_t* H, const int64_t* W)
         if (per && (W[g] % 4))
             return fail(c, MPR_EINVAL, "grid %d: periodic boundary needs W divisible by 4", g);
         const int64_t np = ((W[g] + 1) / 2 + 1) / 2;
-        if (H[g] * np >= ((int64_t)1 << 32)) return fail(c, MPR_EINVAL, "grid %d: too large", g);
+        const int64_t pitch = ((2 * np + 63) / 64) * 64;
+        if (2 * H[g] * pitch >= ((int64_t)1 << 31))
+            return fail(c, MPR_EINVAL, "grid %d: more than 2^30 sites per colour plane", g);
     }
     c->G = G;
     c->C = c->cfg.n_chains;
@@ -555,7 +578,7 @@ static int alloc_device(mpr_ctx* c)
     for (int b = 0; b < 2; ++b) HIPCHK(c, hipMalloc(&c->d_state[b], c->plane_elems * c->elem));
     HIPCHK(c, hipMalloc(&c->d_acc, c->plane_elems * sizeof(double)));
     HIPCHK(c, hipMalloc(&c->d_zcopy, c->n_grid_sites * sizeof(double)));
-    HIPCHK(c, hipMalloc(&c->d_e_part, n_items * sizeof(int64_t)));
+    HIPCHK(c, hipMalloc(&c->d_e_part, 2 * n_items * sizeof(int64_t)));
     HIPCHK(c, hipMalloc(&c->d_a_part, n_items * sizeof(int32_t)));
     HIPCHK(c, hipMalloc(&c->d_flag, sizeof(int)));
     HIPCHK(c, hipMemcpy(c->d_gcs, c->gcs.data(), n_gc * sizeof(GcDesc), hipMemcpyHostToDevice));
@@ -723,7 +746,7 @@ static int load_common(mpr_ctx* c, const double* z, const uint8_t* mask)
         GcCtl& k = ctl[i];
         std::memset(&k, 0, sizeof k);
         k.alpha = c->cfg.alpha0;
-        k.e_smp = -c->cfg.J * ((double)G.e_fix / kTwoPow32) / (double)G.n_sample_bonds;
+        k.e_smp = -c->cfg.J * fix2_value(G.e_hi, G.e_lo) / (double)G.n_sample_bonds;
     }
     HIPCHK(c, hipMemcpy(c->d_gcs, c->gcs.data(), c->gcs.size() * sizeof(GcDesc), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->d_ctl, ctl.data(), ctl.size() * sizeof(GcCtl), hipMemcpyHostToDevice));
@@ -764,12 +787,13 @@ enum { MODE_EQUIL = 0, MODE_AVG = 1, MODE_BURN = 2 };
 
 static SweepFn sweep_fn(const mpr_ctx* c, int flags)
 {
+    const bool per = c->cfg.boundary == MPR_PERIODIC;
     switch (c->sprec) {
-    case MPR_FP64: return c->fsingle ? pick_sweep<double, float>(flags, c->esingle)
-                                     : pick_sweep<double, double>(flags, c->esingle);
-    case MPR_FP32: return c->fsingle ? pick_sweep<float, float>(flags, c->esingle)
-                                     : pick_sweep<float, double>(flags, c->esingle);
-    default: return pick_sweep<_Float16, float>(flags, c->esingle);
+    case MPR_FP64: return c->fsingle ? pick_sweep<double, float>(flags, c->esingle, per)
+                                     : pick_sweep<double, double>(flags, c->esingle, per);
+    case MPR_FP32: return c->fsingle ? pick_sweep<float, float>(flags, c->esingle, per)
+                                     : pick_sweep<float, double>(flags, c->esingle, per);
+    default: return pick_sweep<_Float16, float>(flags, c->esingle, per);
     }
 }
 

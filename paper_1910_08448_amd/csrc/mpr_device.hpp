@@ -67,7 +67,7 @@ struct SweepArgs {
     void* dst;
     double* acc;
     uint8_t* dec;
-    int64_t* e_part;           // per item: energy partial (fixed point, or float bits)
+    int64_t* e_part;           // per item: energy partial [2] (two-word fixed point, or float bits)
     int32_t* a_part;           // per item: accepted moves
     int32_t n_items;
     int32_t sweep_off;         // sweep index = run->base_sweep + sweep_off
@@ -117,7 +117,28 @@ template <> struct Math<float> {
     {
         return __builtin_fmaf((float)(w >> 9), 1.0f / 8388608.0f, 1.0f / 16777216.0f);
     }
-    static __device__ __forceinline__ float atan2(float y, float x) { return atan2f(y, x); }
+    // atan2(y, x) for y >= 0 (the local field's S is a sum of sines of angles in [0, pi]):
+    // octant reduction to a = min/max in [0, 1] and the odd polynomial of Abramowitz & Stegun,
+    // Handbook of Mathematical Functions, formula 4.4.49 (|error| <= 2e-8 on [0, 1]).
+    // (0, 0) gives NaN; callers test for a vanishing field first.
+    static __device__ __forceinline__ float atan2(float y, float x)
+    {
+        const float ax = __builtin_fabsf(x);
+        const float mx = __builtin_fmaxf(ax, y), mn = __builtin_fminf(ax, y);
+        const float t = mn * __builtin_amdgcn_rcpf(mx);
+        const float t2 = t * t;
+        float p = 0.0028662257f;
+        p = __builtin_fmaf(p, t2, -0.0161657367f);
+        p = __builtin_fmaf(p, t2, 0.0429096138f);
+        p = __builtin_fmaf(p, t2, -0.0752896400f);
+        p = __builtin_fmaf(p, t2, 0.1065626393f);
+        p = __builtin_fmaf(p, t2, -0.1420889944f);
+        p = __builtin_fmaf(p, t2, 0.1999355085f);
+        p = __builtin_fmaf(p, t2, -0.3333314528f);
+        float r = __builtin_fmaf(t * t2, p, t);
+        r = (y > ax) ? 1.57079632679489662f - r : r;
+        return (x < 0.0f) ? 3.14159265358979324f - r : r;
+    }
     static __device__ __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 };
 
@@ -142,12 +163,12 @@ template <class S> struct Store;
 template <> struct Store<double> {
     using raw = uint64_t;
     struct pair { raw a, b; };
-    static __device__ __forceinline__ pair load(const void* base, int64_t idx)
+    static __device__ __forceinline__ pair load(const void* base, int idx)
     {
         const ulonglong2 v = *((const ulonglong2*)((const uint64_t*)base + idx));
         return {v.x, v.y};
     }
-    static __device__ __forceinline__ void store(void* base, int64_t idx, pair p)
+    static __device__ __forceinline__ void store(void* base, int idx, pair p)
     {
         *((ulonglong2*)((uint64_t*)base + idx)) = make_ulonglong2(p.a, p.b);
     }
@@ -164,12 +185,12 @@ template <> struct Store<double> {
 template <> struct Store<float> {
     using raw = uint32_t;
     struct pair { raw a, b; };
-    static __device__ __forceinline__ pair load(const void* base, int64_t idx)
+    static __device__ __forceinline__ pair load(const void* base, int idx)
     {
         const uint2 v = *((const uint2*)((const uint32_t*)base + idx));
         return {v.x, v.y};
     }
-    static __device__ __forceinline__ void store(void* base, int64_t idx, pair p)
+    static __device__ __forceinline__ void store(void* base, int idx, pair p)
     {
         *((uint2*)((uint32_t*)base + idx)) = make_uint2(p.a, p.b);
     }
@@ -185,12 +206,12 @@ template <> struct Store<float> {
 template <> struct Store<_Float16> {
     using raw = uint16_t;
     struct pair { raw a, b; };
-    static __device__ __forceinline__ pair load(const void* base, int64_t idx)
+    static __device__ __forceinline__ pair load(const void* base, int idx)
     {
         const uint32_t v = *((const uint32_t*)((const uint16_t*)base + idx));
         return {(raw)(v & 0xffffu), (raw)(v >> 16)};
     }
-    static __device__ __forceinline__ void store(void* base, int64_t idx, pair p)
+    static __device__ __forceinline__ void store(void* base, int idx, pair p)
     {
         *((uint32_t*)((uint16_t*)base + idx)) = (uint32_t)p.a | ((uint32_t)p.b << 16);
     }
@@ -255,15 +276,45 @@ __device__ __forceinline__ SiteOut<S, F> hybrid_update(F u, bool is_free, F C, F
     return o;
 }
 
-// exact 64-bit fixed-point image of an energy term (quantum 2^-32, |e| < 2^19)
-__device__ __forceinline__ int64_t fixed32(double e)
+// Two-word fixed-point image of an energy term, e ~ hi 2^-32 + lo 2^-64 (|e| < 2^18): both
+// words are exact integers, so sums of them do not depend on the order of summation, and the
+// quantum 2^-64 keeps e_sim + J (which can be ~1e-3 at low temperature) exact to the last bit
+// of a double.  Rounding to integers uses the 1.5 * 2^52 shifter.
+struct Fix2 { int64_t hi, lo; };
+
+__device__ __forceinline__ int64_t round_to_i64(double t)    // |t| < 2^51
 {
-    const double t = __builtin_fma(e, 4294967296.0, 6755399441055744.0);
-    return (int64_t)__double_as_longlong(t) - (int64_t)0x4338000000000000ll;
+    const double s = t + 6755399441055744.0;
+    return (int64_t)__double_as_longlong(s) - (int64_t)0x4338000000000000ll;
 }
 
-template <class T> __device__ __forceinline__ T shfl_up1(T v) { return __shfl_up(v, 1, kWave); }
-template <class T> __device__ __forceinline__ T shfl_down1(T v) { return __shfl_down(v, 1, kWave); }
+__device__ __forceinline__ Fix2 fixed64x2(double e)
+{
+    const double t = e * 4294967296.0;                        // exact
+    const int64_t a = round_to_i64(t);
+    const double r = (t - (double)a) * 4294967296.0;          // exact, |r| <= 2^31
+    return Fix2{a, round_to_i64(r)};
+}
+
+// ------------------------------------------------------------------ cross-lane shifts
+// DPP wave shifts by one lane (a plain VALU move, no LDS crossbar): from_left(v) gives lane i
+// the value of lane i-1, from_right(v) the value of lane i+1; lanes without a source get 0.
+__device__ __forceinline__ int dpp_from_left(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_from_right(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ float from_left(float v) { return __int_as_float(dpp_from_left(__float_as_int(v))); }
+__device__ __forceinline__ float from_right(float v) { return __int_as_float(dpp_from_right(__float_as_int(v))); }
+__device__ __forceinline__ double from_left(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_from_left((int)(b & 0xffffffffll)), hi = dpp_from_left((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double from_right(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_from_right((int)(b & 0xffffffffll)), hi = dpp_from_right((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 // per-row data of one lane: (cos, sin) of both pair members, zero where the site is absent
 template <class F> struct RowCS { F c0, s0, c1, s1; };
@@ -275,20 +326,19 @@ template <class F> struct RowCS { F c0, s0, c1, s1; };
 // (cos, sin) of three rows feed the colour-1 update one row behind.  Halo lanes and rows
 // repeat their neighbours' colour-0 updates bit for bit (same inputs, same counters), so
 // items never exchange data within a sweep; the sweep reads `src` and writes `dst`.
-template <class S, class F, int FLAGS, bool ESINGLE>
+template <class S, class F, int FLAGS, bool ESINGLE, bool PER>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
 {
     using St = Store<S>;
     using M = Math<F>;
-    using raw = typename St::raw;
+    using Pair = typename St::pair;
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6));
     if (wid >= a.n_items) return;                 // whole waves leave together
     const Item it = a.items[wid];
     const GcDesc g = a.gcs[it.gc];
     const GcCtl ctl = a.ctl[it.gc];
-    const int64_t sweep = a.run->base_sweep + a.sweep_off;
-    const bool per = a.periodic != 0;
+    const uint32_t sweep = (uint32_t)(a.run->base_sweep + a.sweep_off);
 
     const F q = (F)a.q;
     const F J = (F)a.J;
@@ -297,84 +347,72 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
     // Boltzmann factor exp(-dE/T): float path 2^(dE * (-log2 e / T)), double path exp(dE * (-1/T))
     const F kexp = (sizeof(F) == 4) ? (F)(-1.4426950408889634 / ctl.T) : (F)(-1.0 / ctl.T);
 
+    const int H = g.H, np = g.np, pitch = g.pitch;
     const int j = it.pair0 - 2 + lane;
-    const bool in_range = (j >= 0) & (j < g.np);
-    const int jj = per ? (j + 2 * g.np) % g.np : j;      // periodic: W % 4 == 0, so wc is even
-    const bool lane_ok = per | in_range;
+    const bool in_range = (j >= 0) & (j < np);
+    const int jj = PER ? ((j % np) + np) % np : j;        // periodic: W % 4 == 0, so wc is even
+    const bool lane_ok = PER | in_range;
     const bool out_lane = (lane >= 2) & (lane < kWave - 2) & in_range;
+    // site (y, c, m) of this lane has x = 4 jj + 2 m + ((y + c) & 1); it exists iff x < W
+    const int wl = g.W - 4 * jj;
+    const int col = 2 * jj;                              // plane column of member 0
+    const int plane_sz = H * pitch;                      // < 2^30 (checked on the host)
 
-    const S* src = (const S*)a.src + g.plane_off;
-    S* dst = (S*)a.dst + g.plane_off;
-    const int64_t plane_sz = (int64_t)g.H * g.pitch;
+    const S* __restrict__ src = (const S*)a.src + g.plane_off;
+    S* __restrict__ dst = (S*)a.dst + g.plane_off;
 
-    auto row_ok = [&](int y) -> bool { return per | ((y >= 0) & (y < g.H)); };
-    auto wrap = [&](int y) -> int { return per ? (y + g.H) % g.H : y; };
-    // member m of this lane at row y in colour c exists?
+    auto row_ok = [&](int y) -> bool { return PER | ((y >= 0) & (y < H)); };
+    auto wrap = [&](int y) -> int { return PER ? (y < 0 ? y + H : (y >= H ? y - H : y)) : y; };
     auto exists = [&](int y, int c, int m) -> bool {
-        const int x = 2 * (2 * jj + m) + ((y + c) & 1);
-        return lane_ok & row_ok(y) & (x < g.W);
+        return lane_ok & row_ok(y) & (2 * m + ((y + c) & 1) < wl);
     };
-
-    // raw values of both colours for rows in the window
-    typename St::pair v0_cur, v0_next, v1_m1, v1_0, v1_p1;  // colour-0 old rows k, k+1; colour-1 old rows k-1..k+1
-    RowCS<F> w1_m1, w1_0, w1_p1;    // colour-1 old (cos, sin) rows k-1, k, k+1
-    RowCS<F> w0_m2, w0_m1, w0_0;    // colour-0 new (cos, sin) rows k-2, k-1, k
-    typename St::pair n0_m1, n0_0;  // colour-0 new raw, rows k-1, k
-    int d0_m1a = 0, d0_m1b = 0, d0_0a = 0, d0_0b = 0;   // colour-0 decisions, rows k-1, k
-
-    auto load_pair = [&](int c, int y) -> typename St::pair {
-        typename St::pair p = {0, 0};
-        if (lane_ok & row_ok(y)) p = St::load(src, c * plane_sz + (int64_t)wrap(y) * g.pitch + 2 * jj);
+    auto load_pair = [&](int c, int y) -> Pair {
+        Pair p = {0, 0};
+        if (lane_ok & row_ok(y)) p = St::load(src, c * plane_sz + wrap(y) * pitch + col);
         return p;
     };
-    auto cs_of = [&](typename St::pair p, int y, int c) -> RowCS<F> {
-        RowCS<F> r = {(F)0, (F)0, (F)0, (F)0};
+    auto cs_of = [&](Pair p, int y, int c) -> RowCS<F> {
+        RowCS<F> r;
         F s, co;
         M::sincos_rev(q * St::template value<F>(p.a), s, co);
-        if (exists(y, c, 0)) { r.c0 = co; r.s0 = s; }
+        const bool e0 = exists(y, c, 0), e1 = exists(y, c, 1);
+        r.c0 = e0 ? co : (F)0;
+        r.s0 = e0 ? s : (F)0;
         M::sincos_rev(q * St::template value<F>(p.b), s, co);
-        if (exists(y, c, 1)) { r.c1 = co; r.s1 = s; }
+        r.c1 = e1 ? co : (F)0;
+        r.s1 = e1 ? s : (F)0;
         return r;
     };
 
-    // local field of both members of colour c at row y from the other colour's (cos, sin) rows
-    auto field = [&](const RowCS<F>& up, const RowCS<F>& mid, const RowCS<F>& dn, int y, int c,
-                     F& C0, F& S0, F& C1, F& S1) {
+    // update both members of colour c at row y from the other colour's (cos, sin) rows up, mid,
+    // dn; returns the new raw pair, the (cos, sin) of the new values (zero for absent sites),
+    // the decisions, and the energy of this row's colour-c bonds with their final values
+    auto update_row = [&](Pair old, const RowCS<F>& up, const RowCS<F>& mid, const RowCS<F>& dn,
+                          int y, int c, Pair& nw, RowCS<F>& ncs, int& da, int& db, F& e) {
+        // horizontal neighbours: o == 0 -> member 0 uses (left lane's member 1, own member 0),
+        // member 1 uses (own 0, own 1); o == 1 -> member 0 uses (own 0, own 1), member 1 uses
+        // (own 1, right lane's member 0)
         const int o = (y + c) & 1;
-        // horizontal: o == 0 -> member 0 uses (left lane's member 1, own member 0),
-        //                       member 1 uses (own member 0, own member 1);
-        //             o == 1 -> member 0 uses (own 0, own 1), member 1 uses (own 1, right lane's 0)
-        F hc, hs;
-        if (o == 0) { hc = shfl_up1(mid.c1); hs = shfl_up1(mid.s1); }
-        else        { hc = shfl_down1(mid.c0); hs = shfl_down1(mid.s0); }
+        F C0, S0, C1, S1;
         if (o == 0) {
+            const F hc = from_left(mid.c1), hs = from_left(mid.s1);
             C0 = (hc + mid.c0) + (up.c0 + dn.c0);
             S0 = (hs + mid.s0) + (up.s0 + dn.s0);
             C1 = (mid.c0 + mid.c1) + (up.c1 + dn.c1);
             S1 = (mid.s0 + mid.s1) + (up.s1 + dn.s1);
         } else {
+            const F hc = from_right(mid.c0), hs = from_right(mid.s0);
             C0 = (mid.c0 + mid.c1) + (up.c0 + dn.c0);
             S0 = (mid.s0 + mid.s1) + (up.s0 + dn.s0);
             C1 = (mid.c1 + hc) + (up.c1 + dn.c1);
             S1 = (mid.s1 + hs) + (up.s1 + dn.s1);
         }
-    };
-
-    // update both members of colour c at row y; returns the new raw pair, the (cos, sin) of
-    // the new values (zero for absent sites), the decisions, and the energy of the row's bonds
-    auto update_row = [&](typename St::pair old, const RowCS<F>& up, const RowCS<F>& mid,
-                          const RowCS<F>& dn, int y, int c, typename St::pair& nw,
-                          RowCS<F>& ncs, int& da, int& db, F& e) {
-        F C0, S0, C1, S1;
-        field(up, mid, dn, y, c, C0, S0, C1, S1);
         const bool ex0 = exists(y, c, 0), ex1 = exists(y, c, 1);
         const bool fr0 = ex0 & !St::sample(old.a);
         const bool fr1 = ex1 & !St::sample(old.b);
-        U4 r = {0u, 0u, 0u, 0u};
-        if (fr0 | fr1)
-            r = philox10(U4{(uint32_t)(wrap(y) * g.np + jj), (uint32_t)sweep,
-                            (uint32_t)g.chain_word, (uint32_t)c},
-                         a.key0, a.key1);
+        const U4 r = philox10(U4{(uint32_t)(wrap(y) * np + jj), sweep, (uint32_t)g.chain_word,
+                                 (uint32_t)c},
+                              a.key0, a.key1);
         const F u0 = St::template value<F>(old.a);
         const F u1 = St::template value<F>(old.b);
         const SiteOut<S, F> o0 = hybrid_update<S, F>(u0, fr0, C0, S0, q, inv_piq, J, kexp, alpha, r.x, r.y);
@@ -387,74 +425,71 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
         ncs.s1 = ex1 ? o1.s : (F)0;
         da = o0.dec;
         db = o1.dec;
-        // bonds of this row's colour-c sites, with their final values
         e = M::fma(ncs.c0, C0, ncs.s0 * S0) + M::fma(ncs.c1, C1, ncs.s1 * S1);
     };
 
-    int64_t e_fix = 0;      // fixed-point energy sum (double-precision energy)
-    float e_flt = 0.0f;     // single-precision energy sum
+    int64_t e_hi = 0, e_lo = 0;   // two-word fixed-point energy sum (double-precision energy)
+    float e_flt = 0.0f;           // single-precision energy sum
     int n_acc = 0;
 
     const int ya = it.y0, yb = it.y1;
-    // prologue: old rows ya-2, ya-1 of both colours
-    {
-        typename St::pair a1 = load_pair(1, ya - 2);
-        v1_m1 = a1;                                  // placeholder, shifted below
-        w1_0 = cs_of(a1, ya - 2, 1);
-        v1_0 = a1;
-        typename St::pair b1 = load_pair(1, ya - 1);
-        w1_p1 = cs_of(b1, ya - 1, 1);
-        v1_p1 = b1;
-        v0_next = load_pair(0, ya - 1);
-        w0_m1 = RowCS<F>{(F)0, (F)0, (F)0, (F)0};
-        w0_0 = w0_m1;
-        n0_0 = {0, 0};
-    }
+    const RowCS<F> zero = {(F)0, (F)0, (F)0, (F)0};
+    // window: colour-1 old rows k-1, k, k+1; colour-0 new rows k-2, k-1, k
+    Pair v0_cur, v0_next, v1_m1, v1_0, v1_p1;
+    RowCS<F> w1_m1, w1_0, w1_p1;
+    RowCS<F> w0_m2, w0_m1, w0_0;
+    Pair n0_m1, n0_0;
+    int d0_m1a = 0, d0_m1b = 0, d0_0a = 0, d0_0b = 0;
+
+    v1_0 = load_pair(1, ya - 2);
+    w1_0 = cs_of(v1_0, ya - 2, 1);
+    v1_p1 = load_pair(1, ya - 1);
+    w1_p1 = cs_of(v1_p1, ya - 1, 1);
+    v0_next = load_pair(0, ya - 1);
+    w0_m1 = zero;
+    w0_0 = zero;
+    n0_0 = Pair{0, 0};
+
     // iteration k: load row k+1, colour-0 update of row k, colour-1 update and store of row k-1
     for (int k = ya - 1; k <= yb; ++k) {
-        // shift the window
         w1_m1 = w1_0; w1_0 = w1_p1;
         v1_m1 = v1_0; v1_0 = v1_p1;
         w0_m2 = w0_m1; w0_m1 = w0_0;
         n0_m1 = n0_0;
         d0_m1a = d0_0a; d0_m1b = d0_0b;
         v0_cur = v0_next;
-        // load row k+1
         v1_p1 = load_pair(1, k + 1);
-        w1_p1 = cs_of(v1_p1, k + 1, 1);
         v0_next = load_pair(0, k + 1);
-        // colour-0 update of row k (needs colour-1 old rows k-1, k, k+1)
+        w1_p1 = cs_of(v1_p1, k + 1, 1);
         if (row_ok(k)) {
             F e_unused;
             update_row(v0_cur, w1_m1, w1_0, w1_p1, k, 0, n0_0, w0_0, d0_0a, d0_0b, e_unused);
         } else {
             n0_0 = v0_cur;
-            w0_0 = RowCS<F>{(F)0, (F)0, (F)0, (F)0};
+            w0_0 = zero;
             d0_0a = d0_0b = 0;
         }
-        // colour-1 update of row k-1 (needs colour-0 new rows k-2, k-1, k)
         const int y = k - 1;
         if (y >= ya) {
-            typename St::pair n1;
+            Pair n1;
             RowCS<F> cs1;
             int d1a, d1b;
             F e;
             update_row(v1_m1, w0_m2, w0_m1, w0_0, y, 1, n1, cs1, d1a, d1b, e);
             if (out_lane) {
-                const int64_t r0 = (int64_t)y * g.pitch + 2 * jj;
+                const int r0 = y * pitch + col;
                 St::store(dst, r0, n0_m1);
                 St::store(dst, plane_sz + r0, n1);
-                const bool f0a = exists(y, 0, 0) & !St::sample(n0_m1.a);
-                const bool f0b = exists(y, 0, 1) & !St::sample(n0_m1.b);
-                const bool f1a = exists(y, 1, 0) & !St::sample(n1.a);
-                const bool f1b = exists(y, 1, 1) & !St::sample(n1.b);
-                n_acc += ((d0_m1a & DEC_ACCEPT) ? 1 : 0) + ((d0_m1b & DEC_ACCEPT) ? 1 : 0) +
-                         ((d1a & DEC_ACCEPT) ? 1 : 0) + ((d1b & DEC_ACCEPT) ? 1 : 0);
+                n_acc += ((d0_m1a >> 1) & 1) + ((d0_m1b >> 1) & 1) + ((d1a >> 1) & 1) + ((d1b >> 1) & 1);
                 if (FLAGS & F_ENERGY) {
                     if (ESINGLE) e_flt += (float)e;
-                    else e_fix += fixed32((double)e);
+                    else { const Fix2 f = fixed64x2((double)e); e_hi += f.hi; e_lo += f.lo; }
                 }
                 if (FLAGS & F_ACC) {
+                    const bool f0a = exists(y, 0, 0) & !St::sample(n0_m1.a);
+                    const bool f0b = exists(y, 0, 1) & !St::sample(n0_m1.b);
+                    const bool f1a = exists(y, 1, 0) & !St::sample(n1.a);
+                    const bool f1b = exists(y, 1, 1) & !St::sample(n1.b);
                     double* acc = a.acc + g.plane_off;
                     double2 p0 = *((double2*)(acc + r0));
                     double2 p1 = *((double2*)(acc + plane_sz + r0));
@@ -469,10 +504,10 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
                     uint8_t* d = a.dec + g.site_off + (int64_t)y * g.W;
                     const int xb = 4 * jj;
                     const int o0 = y & 1, o1 = (y + 1) & 1;
-                    if (exists(y, 0, 0)) d[xb + o0] = f0a ? (uint8_t)d0_m1a : 0;
-                    if (exists(y, 0, 1)) d[xb + 2 + o0] = f0b ? (uint8_t)d0_m1b : 0;
-                    if (exists(y, 1, 0)) d[xb + o1] = f1a ? (uint8_t)d1a : 0;
-                    if (exists(y, 1, 1)) d[xb + 2 + o1] = f1b ? (uint8_t)d1b : 0;
+                    if (exists(y, 0, 0)) d[xb + o0] = (uint8_t)d0_m1a;
+                    if (exists(y, 0, 1)) d[xb + 2 + o0] = (uint8_t)d0_m1b;
+                    if (exists(y, 1, 0)) d[xb + o1] = (uint8_t)d1a;
+                    if (exists(y, 1, 1)) d[xb + 2 + o1] = (uint8_t)d1b;
                 }
             }
         }
@@ -483,12 +518,15 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
         n_acc += __shfl_xor(n_acc, off, kWave);
         if (FLAGS & F_ENERGY) {
             if (ESINGLE) e_flt += __shfl_xor(e_flt, off, kWave);
-            else e_fix += __shfl_xor(e_fix, off, kWave);
+            else { e_hi += __shfl_xor(e_hi, off, kWave); e_lo += __shfl_xor(e_lo, off, kWave); }
         }
     }
     if (lane == 0) {
         a.a_part[wid] = n_acc;
-        if (FLAGS & F_ENERGY) a.e_part[wid] = ESINGLE ? (int64_t)__float_as_uint(e_flt) : e_fix;
+        if (FLAGS & F_ENERGY) {
+            a.e_part[2 * wid] = ESINGLE ? (int64_t)__float_as_uint(e_flt) : e_hi;
+            a.e_part[2 * wid + 1] = ESINGLE ? 0 : e_lo;
+        }
     }
 }
 
