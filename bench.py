@@ -11,6 +11,7 @@ Also printed in the same JSON line:
                 prediction sites read and written: (N + 2P) s per chain, s = bytes per angle)
                 over its average launch time, measured with HIP events on the library's stream
   cpu_baseline  the FP64 CPU oracle timed on a bounded sample of the same workload
+  setups        the same measurements for the other precision setups / workloads
 """
 import argparse
 import json
@@ -28,132 +29,124 @@ from paper_1910_08448_amd import synth  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 PREC = {"fp64": 0, "fp32": 1, "fp16": 2}
 BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
+DTYPE = {"fp64": "f64", "fp32": "f32", "fp16": "f16"}
 SWEEPS = {"grid64": (256, 100), "grid1024": (1000, 100), "grid4096": (1000, 100),
           "grid16384": (500, 50), "batch256": (1000, 100)}
+CHAINS = {"batch256": 4}
+EXTENDED = [("grid4096", "fp16"), ("grid16384", "fp16"), ("grid16384", "fp32"),
+            ("grid16384", "fp64"), ("batch256", "fp16"), ("batch256", "fp32")]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def make_inputs(name, p_missing):
+    t = time.time()
     if name == "batch256":
         grids = synth.batch_workload(256, 64, 1024, seed=1)
-        return {"grids": grids, "mc_seed": 2001}
-    w = synth.workload(name, seed=1, p_missing=p_missing)
-    return {"grids": [w], "mc_seed": w["mc_seed"]}
+        inp = {"grids": grids, "mc_seed": 2001}
+    else:
+        w = synth.workload(name, seed=1, p_missing=p_missing)
+        inp = {"grids": [w], "mc_seed": w["mc_seed"]}
+    log("inputs %s generated in %.1f s" % (name, time.time() - t))
+    return inp
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="grid1024", choices=sorted(SWEEPS))
-    ap.add_argument("--precision", default="fp32", choices=sorted(PREC))
-    ap.add_argument("--p-missing", type=float, default=None)
-    ap.add_argument("--chains", type=int, default=None)
-    ap.add_argument("--kernel-launches", type=int, default=20)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the method on a single MI355X "
-              "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
+class Inputs:
+    """Synthetic inputs of one workload, resident in HBM."""
 
-    import torch
-    from paper_1910_08448_amd import mpr as M
+    def __init__(self, name, p_missing, torch):
+        self.name = name
+        self.p_missing = p_missing
+        inp = make_inputs(name, p_missing)
+        self.grids = inp["grids"]
+        self.mc_seed = inp["mc_seed"]
+        self.shapes = [g["z"].shape for g in self.grids]
+        self.z = torch.as_tensor(np.concatenate([g["z"].ravel() for g in self.grids])).cuda()
+        self.m = torch.as_tensor(np.concatenate([g["mask"].ravel() for g in self.grids])).cuda()
+        self.n_sites = [h * w for h, w in self.shapes]
+        self.n_pred = [int((g["mask"] == 0).sum()) for g in self.grids]
 
-    torch.cuda.set_device(0)
-    n_equil, n_avg = SWEEPS[args.workload]
-    chains = args.chains or (4 if args.workload == "batch256" else 1)
-    inp = make_inputs(args.workload, args.p_missing)
-    grids = inp["grids"]
-    shapes = [g["z"].shape for g in grids]
-    z_d = torch.as_tensor(np.concatenate([g["z"].ravel() for g in grids])).cuda()
-    m_d = torch.as_tensor(np.concatenate([g["mask"].ravel() for g in grids])).cuda()
-    n_sites = [h * w for h, w in shapes]
-    n_pred = [int((g["mask"] == 0).sum()) for g in grids]
-    P = sum(n_pred) * chains
-    sweeps = n_equil + n_avg
-    updates_per_step = P * sweeps
 
+def oracle_reference(name, p_missing):
+    path = os.path.join(ROOT, "tests", "golden", "oracle_reference.json")
+    if name != "grid1024" or not os.path.exists(path):
+        return None
+    key = "grid1024_p%.2f" % (0.33 if p_missing is None else p_missing)
+    return json.load(open(path)).get(key)
+
+
+def measure(inp, precision, steps, warmup, kernel_launches, torch, M):
+    chains = CHAINS.get(inp.name, 1)
+    n_equil, n_avg = SWEEPS[inp.name]
+    P = sum(inp.n_pred) * chains
+    updates_per_step = P * (n_equil + n_avg)
     stream = torch.cuda.Stream()
-    ctx = M.Context(shapes=shapes, stream=stream, precision=PREC[args.precision],
-                    n_chains=chains, seed=inp["mc_seed"])
-    zhat = torch.empty(sum(n_sites), dtype=torch.float64, device="cuda")
+    ctx = M.Context(shapes=inp.shapes, stream=stream, precision=PREC[precision], n_chains=chains,
+                    seed=inp.mc_seed)
+    zhat = torch.empty(sum(inp.n_sites), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
 
     def step():
         with torch.cuda.stream(stream):
-            ctx.batch_load(z_d, m_d)
+            ctx.batch_load(inp.z, inp.m)
             ctx.infer_temperature(n_equil, want_T=False)
             ctx.run(n_avg)
             ctx.predictions(out=zhat)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = updates_per_step * args.steps / elapsed
-    print("[bench] %d steps of %s/%s: %.3f ms/step, %.4g site-updates/s"
-          % (args.steps, args.workload, args.precision, ms_per_step, value), file=sys.stderr, flush=True)
+    ms_per_step = 1e3 * elapsed / steps
+    value = updates_per_step * steps / elapsed
+    log("%d steps of %s/%s: %.3f ms/step, %.4g site-updates/s"
+        % (steps, inp.name, precision, ms_per_step, value))
 
-    # accuracy of the last step against the truth
     zh = zhat.cpu().numpy()
-    errs, sq = [], []
-    off = 0
-    for g, n in zip(grids, n_sites):
+    errs, off = [], 0
+    for g, n in zip(inp.grids, inp.n_sites):
         m = (g["mask"] == 0).ravel()
-        d = zh[off:off + n][m] - g["truth"].ravel()[m]
-        errs.append(np.abs(d))
+        errs.append(zh[off:off + n][m] - g["truth"].ravel()[m])
         off += n
     err = np.concatenate(errs)
-    mae = float(err.mean())
-    rmse = float(np.sqrt((err ** 2).mean()))
-    stats = ctx.stats()
-    T_hat = [s["T"] for s in stats]
+    mae, rmse = float(np.abs(err).mean()), float(np.sqrt((err ** 2).mean()))
+    T_hat = [s["T"] for s in ctx.stats()]
 
-    # sweep-kernel timing with HIP events on the library's stream
+    # the sweep kernel alone, timed with HIP events on the library's stream
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    nl = args.kernel_launches
     with torch.cuda.stream(stream):
         ctx.bench_sweeps(2)
         ev0.record(stream)
-        ctx.bench_sweeps(nl)
+        ctx.bench_sweeps(kernel_launches)
         ev1.record(stream)
     ev1.synchronize()
-    kernel_ms = ev0.elapsed_time(ev1) / nl
-    s = BYTES[args.precision]
-    alg_bytes = sum((n + 2 * p) * s for n, p in zip(n_sites, n_pred)) * chains
+    kernel_ms = ev0.elapsed_time(ev1) / kernel_launches
+    s = BYTES[precision]
+    alg_bytes = sum((n + 2 * p) * s for n, p in zip(inp.n_sites, inp.n_pred)) * chains
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "kernel": "k_sweep (inference variant)", "kernel_ms": round(kernel_ms, 5),
-                "bytes_per_launch": alg_bytes}
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(grids[0], inp["mc_seed"], args.cpu_seconds)
-
-    out = {
-        "metric": "site-updates/s per precision setup (FP64/FP32/FP16) and prediction MAE vs FP64",
-        "value": value, "unit": "site-updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f16"}[args.precision],
-        "data": "synthetic",
-        "config": {"workload": args.workload, "precision": args.precision,
-                   "grids": len(shapes), "sites": sum(n_sites), "prediction_sites": sum(n_pred),
-                   "chains": chains, "n_equil": n_equil, "n_avg": n_avg},
-        "mae": mae, "rmse": rmse, "T_hat": T_hat[:4],
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
+                "bytes_per_launch": alg_bytes,
+                "site_updates_per_launch": P}
     ctx.close()
+    out = {"workload": inp.name, "precision": precision, "value": value,
+           "unit": "site-updates/s", "ms_per_step": ms_per_step, "steps": steps,
+           "grids": len(inp.shapes), "sites": sum(inp.n_sites), "prediction_sites": sum(inp.n_pred),
+           "chains": chains, "n_equil": n_equil, "n_avg": n_avg, "mae": mae, "rmse": rmse,
+           "T_hat": T_hat[:4], "roofline": roofline}
+    ref = oracle_reference(inp.name, inp.p_missing)
+    if ref is not None and chains == ref["chains"]:
+        out["oracle_mae"] = ref["mae"]
+        out["mae_vs_oracle"] = mae / ref["mae"] - 1.0
+    return out
 
 
 def cpu_baseline(grid, seed, seconds):
@@ -180,6 +173,86 @@ def cpu_baseline(grid, seed, seconds):
     return {"value": n_pred * n / dt, "unit": "site-updates/s", "cores": cores, "kind": "oracle",
             "sample": "first %d inference sweeps of grid 0 (%dx%d, %d prediction sites), 1 chain, FP64"
                       % (n, grid["z"].shape[0], grid["z"].shape[1], n_pred)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="grid1024", choices=sorted(SWEEPS))
+    ap.add_argument("--precision", default="fp32", choices=sorted(PREC))
+    ap.add_argument("--p-missing", type=float, default=None)
+    ap.add_argument("--kernel-launches", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-setups", action="store_true", help="only the primary setup")
+    ap.add_argument("--extended", action="store_true",
+                    help="also the 4096^2, 16384^2 and 256-grid batched workloads")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="copy a buffer of this many MiB once (calibrates HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs the method on a single MI355X "
+              "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1910_08448_amd import mpr as M
+
+    torch.cuda.set_device(0)
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy probe: %d MiB read + %d MiB written" % (args.copy_probe_mib, args.copy_probe_mib))
+        del a, b
+    inputs = {args.workload: Inputs(args.workload, args.p_missing, torch)}
+    prim = measure(inputs[args.workload], args.precision, args.steps, args.warmup,
+                   args.kernel_launches, torch, M)
+
+    setups = []
+    if not args.no_setups:
+        todo = [(args.workload, p) for p in ("fp64", "fp32", "fp16") if p != args.precision]
+        if args.extended:
+            todo += EXTENDED
+        for wl, prec in todo:
+            if wl not in inputs:
+                for k in list(inputs):
+                    if k != args.workload:
+                        del inputs[k]
+                torch.cuda.empty_cache()
+                inputs[wl] = Inputs(wl, None, torch)
+            steps = max(1, min(args.steps, 3)) if wl != args.workload else args.steps
+            setups.append(measure(inputs[wl], prec, steps, 1, args.kernel_launches, torch, M))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        g0 = inputs[args.workload].grids[0]
+        cpu = cpu_baseline(g0, inputs[args.workload].mc_seed, args.cpu_seconds)
+
+    out = {
+        "metric": "site-updates/s per precision setup (FP64/FP32/FP16) and prediction MAE vs FP64",
+        "value": prim["value"], "unit": "site-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": prim["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.precision],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "precision": args.precision,
+                   "grids": prim["grids"], "sites": prim["sites"],
+                   "prediction_sites": prim["prediction_sites"], "chains": prim["chains"],
+                   "n_equil": prim["n_equil"], "n_avg": prim["n_avg"]},
+        "mae": prim["mae"], "rmse": prim["rmse"], "T_hat": prim["T_hat"],
+        "roofline": prim["roofline"],
+        "cpu_baseline": cpu,
+        "setups": setups,
+    }
+    for k in ("oracle_mae", "mae_vs_oracle"):
+        if k in prim:
+            out[k] = prim[k]
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

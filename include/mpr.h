@@ -83,7 +83,7 @@ typedef struct mpr_config {
     double alpha0;            /* initial Metropolis window, fraction of a turn, (0, 1] */
     double acc_target;        /* acceptance rate the window control aims at, (0, 1)    */
     double T_min, T_max;      /* temperature clamp, 0 < T_min <= T_max                 */
-    int32_t tile_rows;        /* rows per work item, 0 = automatic                     */
+    int32_t tile_rows;        /* rows per work item, 0 = heuristic, -1 = autotune at load */
     int32_t graph_sweeps;     /* sweeps per captured HIP graph, 0 = automatic,
                                  -1 = launch kernels without graphs                   */
     int32_t reserved[6];
@@ -177,6 +177,13 @@ int mpr_debug_sweep(mpr_ctx* ctx, int32_t sweep, uint8_t* decisions_dev);
  * temperatures and windows, without the control step: for timing the kernel alone with events
  * recorded on the context's stream.  Advances the state and the sweep index like burn-in. */
 int mpr_bench_sweeps(mpr_ctx* ctx, int32_t n);
+
+/* Picks the rows per work item of the sweep kernel by timing n_sweeps inference sweeps for each
+ * candidate (4 ... 256) from the current state, which is restored afterwards; results do not
+ * depend on the choice.  Winners are remembered per shape and precision in the process, and in
+ * the text file named by the environment variable MPR_TUNE_CACHE if it is set.  mpr_config
+ * tile_rows = -1 runs it at load (8 sweeps).  *rows_out (may be NULL) receives the choice. */
+int mpr_autotune(mpr_ctx* ctx, int32_t n_sweeps, int32_t* rows_out);
 
 /* Number of grids, chains and sites of a context (any pointer may be NULL). */
 int mpr_get_shape(mpr_ctx* ctx, int32_t* n_grids, int32_t* n_chains, int64_t* n_sites);

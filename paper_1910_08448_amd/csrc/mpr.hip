@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -414,6 +415,8 @@ struct mpr_ctx {
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;   // (mode, cur) -> graph of K sweeps
     int graph_k = 0;
     std::vector<int64_t> alloc_sig;                          // shapes the buffers were sized for
+    int rows = 16;                                           // rows per work item
+    int64_t item_cap = 0;                                    // items at the smallest row block
 };
 
 static const char* kStatusText[] = {
@@ -457,7 +460,7 @@ static int check_config(const mpr_config* c)
     if (!(c->alpha0 > 0.0 && c->alpha0 <= 1.0)) return MPR_EINVAL;
     if (!(c->acc_target > 0.0 && c->acc_target < 1.0)) return MPR_EINVAL;
     if (!(c->T_min > 0.0) || !(c->T_max >= c->T_min) || !std::isfinite(c->T_max)) return MPR_EINVAL;
-    if (c->tile_rows < 0 || c->grid_offset < 0) return MPR_EINVAL;
+    if (c->tile_rows < -1 || c->grid_offset < 0) return MPR_EINVAL;
     return MPR_OK;
 }
 
@@ -479,21 +482,57 @@ static void free_device(mpr_ctx* c)
 }
 
 // work items: per (grid, chain), row blocks of `rows` rows x strips of 60 lane pairs
+static int64_t count_items(const mpr_ctx* c, int rows)
+{
+    int64_t n = 0;
+    for (int g = 0; g < c->G; ++g) {
+        const int64_t np = ((c->W[g] + 1) / 2 + 1) / 2;
+        n += c->C * ((np + kOutPairs - 1) / kOutPairs) * ((c->H[g] + rows - 1) / rows);
+    }
+    return n;
+}
+
+// Heuristic cost of a row-block size: a wave walks rows + 2 colour-0 rows (+ fixed work), and
+// the 1024 SIMDs (256 CUs x 4) run the items in ceil(items / 1024) rounds.
+static double rows_cost(const mpr_ctx* c, int rows)
+{
+    const double rounds = std::ceil((double)count_items(c, rows) / 1024.0);
+    return rounds * (rows + 3.5);
+}
+
+static const int kRowCandidates[] = {2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32, 40, 48,
+                                     56, 64, 80, 96, 112, 128, 160, 192, 224, 256};
+
 static int choose_rows(const mpr_ctx* c)
 {
     if (c->cfg.tile_rows > 0) return c->cfg.tile_rows;
-    int64_t base = 0;
-    for (int g = 0; g < c->G; ++g) {
-        const int64_t np = ((c->W[g] + 1) / 2 + 1) / 2;
-        base += c->C * ((np + kOutPairs - 1) / kOutPairs) * c->H[g];
+    // large workloads: 64-row items keep >= 16 waves per SIMD in flight (measured best on
+    // 16384^2); small ones: the round model above
+    if (count_items(c, 64) >= 16 * 1024) return 64;
+    int maxH = 0;
+    for (int g = 0; g < c->G; ++g) maxH = std::max<int>(maxH, (int)c->H[g]);
+    int best = 4;
+    double best_cost = 1e300;
+    for (int r : kRowCandidates) {
+        if (r > maxH && r > 2) break;
+        const double cost = rows_cost(c, r);
+        if (cost < best_cost * 0.999) { best_cost = cost; best = r; }
     }
-    // aim at >= 4096 waves (4 per SIMD of the 1024 SIMDs) while keeping the 4 halo rows of an
-    // item small against its rows
-    int64_t rows = base / 4096;
-    rows = std::max<int64_t>(4, std::min<int64_t>(128, rows));
-    int r = 4;
-    while (r * 2 <= rows) r *= 2;
-    return r;
+    return best;
+}
+
+// work items of every (grid, chain): row blocks of `rows` rows x strips of 60 lane pairs
+static void build_items(mpr_ctx* c, int rows)
+{
+    c->items.clear();
+    for (size_t i = 0; i < c->gcs.size(); ++i) {
+        GcDesc& d = c->gcs[i];
+        d.item_begin = (int32_t)c->items.size();
+        for (int y0 = 0; y0 < d.H; y0 += rows)
+            for (int p0 = 0; p0 < d.np; p0 += kOutPairs)
+                c->items.push_back(Item{(int32_t)i, p0, y0, std::min(d.H, y0 + rows)});
+        d.item_end = (int32_t)c->items.size();
+    }
 }
 
 static int setup_shapes(mpr_ctx* c, int G, const int64_t* H, const int64_t* W)
@@ -521,9 +560,7 @@ static int setup_shapes(mpr_ctx* c, int G, const int64_t* H, const int64_t* W)
     int64_t off = 0;
     for (int g = 0; g < G; ++g) { c->site_off[g] = off; off += H[g] * W[g]; }
     c->n_grid_sites = off;
-    const int rows = choose_rows(c);
     c->gcs.clear();
-    c->items.clear();
     int64_t plane = 0;
     for (int g = 0; g < G; ++g)
         for (int ch = 0; ch < c->C; ++ch) {
@@ -537,16 +574,16 @@ static int setup_shapes(mpr_ctx* c, int G, const int64_t* H, const int64_t* W)
             d.grid = g;
             d.plane_off = plane;
             plane += 2 * (int64_t)d.H * d.pitch;
-            d.site_off = (int64_t)(g * c->C + ch) * 0;   // fixed below
             d.grid_site_off = c->site_off[g];
             d.n_bonds = per ? 2 * H[g] * W[g] : 2 * H[g] * W[g] - H[g] - W[g];
-            d.item_begin = (int32_t)c->items.size();
-            for (int y0 = 0; y0 < d.H; y0 += rows)
-                for (int p0 = 0; p0 < d.np; p0 += kOutPairs)
-                    c->items.push_back(Item{(int32_t)c->gcs.size(), p0, y0, std::min(d.H, y0 + rows)});
-            d.item_end = (int32_t)c->items.size();
             c->gcs.push_back(d);
         }
+    c->rows = choose_rows(c);
+    build_items(c, c->rows);
+    const int rmin = std::min(c->rows, 2);
+    c->item_cap = 0;
+    for (const auto& d : c->gcs)
+        c->item_cap += (int64_t)((d.np + kOutPairs - 1) / kOutPairs) * ((d.H + rmin - 1) / rmin);
     // per-chain packed site offsets: [g][chain][H*W]
     int64_t so = 0;
     for (int g = 0; g < G; ++g)
@@ -555,22 +592,33 @@ static int setup_shapes(mpr_ctx* c, int G, const int64_t* H, const int64_t* W)
     return MPR_OK;
 }
 
+// host -> device copy ordered on the context's stream (the caller's stream may be a
+// non-blocking stream, which a plain hipMemcpy on the null stream would not wait for); the
+// stream is synchronised so the host buffer may be released right after
+static hipError_t h2d(mpr_ctx* c, void* dst, const void* src, size_t bytes)
+{
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(c->stream);
+}
+
 static int alloc_device(mpr_ctx* c)
 {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     const size_t n_gc = c->gcs.size(), n_items = c->items.size();
     // a reload with the same shapes reuses every buffer (and the captured graphs)
-    std::vector<int64_t> sig = {(int64_t)n_gc, (int64_t)n_items, c->plane_elems, c->n_grid_sites};
+    std::vector<int64_t> sig = {(int64_t)n_gc, (int64_t)n_items, c->plane_elems, c->n_grid_sites, c->rows};
     for (int g = 0; g < c->G; ++g) { sig.push_back(c->H[g]); sig.push_back(c->W[g]); }
     if (c->d_gcs && sig == c->alloc_sig) {
-        HIPCHK(c, hipMemcpy(c->d_gcs, c->gcs.data(), n_gc * sizeof(GcDesc), hipMemcpyHostToDevice));
+        HIPCHK(c, h2d(c, c->d_gcs, c->gcs.data(), n_gc * sizeof(GcDesc)));
         RunCtl r{0, 0, 0, 0};
-        HIPCHK(c, hipMemcpy(c->d_run, &r, sizeof r, hipMemcpyHostToDevice));
+        HIPCHK(c, h2d(c, c->d_run, &r, sizeof r));
         return MPR_OK;
     }
     free_device(c);
     c->alloc_sig = sig;
     HIPCHK(c, hipMalloc(&c->d_gcs, n_gc * sizeof(GcDesc)));
-    HIPCHK(c, hipMalloc(&c->d_items, n_items * sizeof(Item)));
+    HIPCHK(c, hipMalloc(&c->d_items, c->item_cap * sizeof(Item)));
     HIPCHK(c, hipMalloc(&c->d_ctl, n_gc * sizeof(GcCtl)));
     HIPCHK(c, hipMalloc(&c->d_run, sizeof(RunCtl)));
     HIPCHK(c, hipMalloc(&c->d_dbg_run, sizeof(RunCtl)));
@@ -578,14 +626,14 @@ static int alloc_device(mpr_ctx* c)
     for (int b = 0; b < 2; ++b) HIPCHK(c, hipMalloc(&c->d_state[b], c->plane_elems * c->elem));
     HIPCHK(c, hipMalloc(&c->d_acc, c->plane_elems * sizeof(double)));
     HIPCHK(c, hipMalloc(&c->d_zcopy, c->n_grid_sites * sizeof(double)));
-    HIPCHK(c, hipMalloc(&c->d_e_part, 2 * n_items * sizeof(int64_t)));
-    HIPCHK(c, hipMalloc(&c->d_a_part, n_items * sizeof(int32_t)));
+    HIPCHK(c, hipMalloc(&c->d_e_part, 2 * c->item_cap * sizeof(int64_t)));
+    HIPCHK(c, hipMalloc(&c->d_a_part, c->item_cap * sizeof(int32_t)));
     HIPCHK(c, hipMalloc(&c->d_flag, sizeof(int)));
-    HIPCHK(c, hipMemcpy(c->d_gcs, c->gcs.data(), n_gc * sizeof(GcDesc), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(c->d_items, c->items.data(), n_items * sizeof(Item), hipMemcpyHostToDevice));
+    HIPCHK(c, h2d(c, c->d_gcs, c->gcs.data(), n_gc * sizeof(GcDesc)));
+    HIPCHK(c, h2d(c, c->d_items, c->items.data(), n_items * sizeof(Item)));
     RunCtl r{0, 0, 0, 0};
-    HIPCHK(c, hipMemcpy(c->d_run, &r, sizeof r, hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(c->d_dbg_run, &r, sizeof r, hipMemcpyHostToDevice));
+    HIPCHK(c, h2d(c, c->d_run, &r, sizeof r));
+    HIPCHK(c, h2d(c, c->d_dbg_run, &r, sizeof r));
     return MPR_OK;
 }
 
@@ -698,6 +746,8 @@ static int usable(mpr_ctx* c)
     return MPR_OK;
 }
 
+static int autotune(mpr_ctx* c, int n, int* best_out);
+
 static int load_common(mpr_ctx* c, const double* z, const uint8_t* mask)
 {
     int rc = alloc_device(c);
@@ -748,13 +798,14 @@ static int load_common(mpr_ctx* c, const double* z, const uint8_t* mask)
         k.alpha = c->cfg.alpha0;
         k.e_smp = -c->cfg.J * fix2_value(G.e_hi, G.e_lo) / (double)G.n_sample_bonds;
     }
-    HIPCHK(c, hipMemcpy(c->d_gcs, c->gcs.data(), c->gcs.size() * sizeof(GcDesc), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(c->d_ctl, ctl.data(), ctl.size() * sizeof(GcCtl), hipMemcpyHostToDevice));
+    HIPCHK(c, h2d(c, c->d_gcs, c->gcs.data(), c->gcs.size() * sizeof(GcDesc)));
+    HIPCHK(c, h2d(c, c->d_ctl, ctl.data(), ctl.size() * sizeof(GcCtl)));
     c->cur = 0;
     c->next_sweep = 0;
     c->n_avg = 0;
     c->trace_len = 0;
     c->phase = PH_LOADED;
+    if (c->cfg.tile_rows == -1) return autotune(c, 8, nullptr);
     return MPR_OK;
 }
 
@@ -1111,6 +1162,121 @@ int mpr_bench_sweeps(mpr_ctx* c, int32_t n)
     c->next_sweep += n;
     HIPCHK(c, hipGetLastError());
     return MPR_OK;
+}
+
+// ------------------------------------------------------------------ autotuning
+// Rows per work item trade parallelism (more, shorter items) against the 4 halo rows each item
+// recomputes.  The sweep's results do not depend on the choice (tested bitwise), so the tuner
+// may pick any candidate; it times n inference sweeps per candidate from a saved state, restores
+// the state, and remembers the winner per shape signature (in memory, and in the text file named
+// by MPR_TUNE_CACHE if set).
+static std::map<std::string, int>& tune_cache()
+{
+    static std::map<std::string, int> m;
+    static bool loaded = false;
+    if (!loaded) {
+        loaded = true;
+        if (const char* path = std::getenv("MPR_TUNE_CACHE")) {
+            if (FILE* f = std::fopen(path, "r")) {
+                char key[256];
+                int rows;
+                while (std::fscanf(f, "%255s %d", key, &rows) == 2) m[key] = rows;
+                std::fclose(f);
+            }
+        }
+    }
+    return m;
+}
+
+static std::string tune_key(const mpr_ctx* c)
+{
+    uint64_t h = 1469598103934665603ull;
+    for (int g = 0; g < c->G; ++g)
+        for (int64_t v : {c->H[g], c->W[g]}) { h ^= (uint64_t)v; h *= 1099511628211ull; }
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "s%d_f%d_e%d_b%d_c%d_g%d_%016llx", c->sprec, (int)c->fsingle,
+                  (int)c->esingle, c->cfg.boundary, c->C, c->G, (unsigned long long)h);
+    return buf;
+}
+
+static int use_rows(mpr_ctx* c, int rows)
+{
+    c->rows = rows;
+    build_items(c, rows);
+    if ((int64_t)c->items.size() > c->item_cap) return fail(c, MPR_EINVAL, "too many work items");
+    HIPCHK(c, h2d(c, c->d_items, c->items.data(), c->items.size() * sizeof(Item)));
+    HIPCHK(c, h2d(c, c->d_gcs, c->gcs.data(), c->gcs.size() * sizeof(GcDesc)));
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    c->alloc_sig.clear();     // buffers stay, but a reload must rebuild the signature
+    return MPR_OK;
+}
+
+static int autotune(mpr_ctx* c, int n, int* best_out)
+{
+    const std::string key = tune_key(c);
+    auto& cache = tune_cache();
+    auto hit = cache.find(key);
+    if (hit != cache.end()) {
+        if (best_out) *best_out = hit->second;
+        return use_rows(c, hit->second);
+    }
+    int maxH = 0;
+    for (int g = 0; g < c->G; ++g) maxH = std::max<int>(maxH, (int)c->H[g]);
+    void* saved = nullptr;
+    HIPCHK(c, hipMalloc(&saved, c->plane_elems * c->elem));
+    HIPCHK(c, hipMemcpyAsync(saved, c->d_state[c->cur], c->plane_elems * c->elem, hipMemcpyDeviceToDevice, c->stream));
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    // candidates: the six best row counts of the cost model
+    std::vector<std::pair<double, int>> ranked;
+    for (int r : kRowCandidates) {
+        if (r > maxH && r > 2) break;
+        ranked.push_back({rows_cost(c, r), r});
+    }
+    std::sort(ranked.begin(), ranked.end());
+    if (ranked.size() > 6) ranked.resize(6);
+    int best = c->rows;
+    float best_ms = 1e30f;
+    for (const auto& cand : ranked) {
+        const int r = cand.second;
+        int rc = use_rows(c, r);
+        if (rc) { (void)hipFree(saved); return rc; }
+        int buf = c->cur;
+        enqueue_sweep(c, F_ENERGY, 0, buf, c->d_run, nullptr);   // warm-up
+        buf ^= 1;
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        for (int i = 0; i < n; ++i) { enqueue_sweep(c, F_ENERGY, 0, buf, c->d_run, nullptr); buf ^= 1; }
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) { best_ms = ms; best = r; }
+        HIPCHK(c, hipMemcpyAsync(c->d_state[c->cur], saved, c->plane_elems * c->elem, hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(saved);
+    cache[key] = best;
+    if (const char* path = std::getenv("MPR_TUNE_CACHE")) {
+        if (FILE* f = std::fopen(path, "a")) { std::fprintf(f, "%s %d\n", key.c_str(), best); std::fclose(f); }
+    }
+    if (best_out) *best_out = best;
+    return use_rows(c, best);
+}
+
+int mpr_autotune(mpr_ctx* c, int32_t n_sweeps, int32_t* rows_out)
+{
+    int rc = usable(c);
+    if (rc) return rc;
+    if (c->phase < PH_LOADED) return fail(c, MPR_ESTATE, "no data loaded");
+    if (n_sweeps < 1) return fail(c, MPR_EINVAL, "n_sweeps must be >= 1");
+    int best = 0;
+    rc = autotune(c, n_sweeps, &best);
+    if (rows_out) *rows_out = best;
+    return rc;
 }
 
 int mpr_get_shape(mpr_ctx* c, int32_t* n_grids, int32_t* n_chains, int64_t* n_sites)

@@ -61,6 +61,7 @@ _SIG = {
     "mpr_set_state": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "mpr_debug_sweep": (ctypes.c_int, [_vp, _i32, _vp]),
     "mpr_bench_sweeps": (ctypes.c_int, [_vp, _i32]),
+    "mpr_autotune": (ctypes.c_int, [_vp, _i32, _vp]),
     "mpr_get_shape": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "mpr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "mpr_last_error": (ctypes.c_char_p, [_vp]),
@@ -184,6 +185,11 @@ class Context:
 
     def burn_in(self, n):
         self._call("mpr_burn_in", _lib.mpr_burn_in, n)
+
+    def autotune(self, n_sweeps=8):
+        rows = ctypes.c_int32()
+        self._call("mpr_autotune", _lib.mpr_autotune, n_sweeps, ctypes.byref(rows))
+        return rows.value
 
     def bench_sweeps(self, n):
         self._call("mpr_bench_sweeps", _lib.mpr_bench_sweeps, n)

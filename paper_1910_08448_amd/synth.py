@@ -8,22 +8,33 @@ covariance on square grids, a fraction of the sites removed at random), generali
 Whittle-Matern family: in two dimensions the spectral density (kappa^2 + |k|^2)^-(nu + 1)
 with nu = 1/2 gives the exponential covariance sigma^2 exp(-kappa |h|), kappa = 1/xi.
 """
+import os
+
 import numpy as np
 
 
 def grf(H, W, nu=0.5, xi=8.0, seed=1):
     """Zero-mean, unit-variance stationary Gaussian field on an H x W torus by FFT spectral
     synthesis with the Whittle-Matern density (kappa^2 + |k|^2)^-(nu+1), kappa = 1/xi."""
+    import scipy.fft
     rng = np.random.default_rng(seed)
     noise = rng.standard_normal((H, W))
     ky = 2.0 * np.pi * np.fft.fftfreq(H)
-    kx = 2.0 * np.pi * np.fft.fftfreq(W)
-    k2 = ky[:, None] ** 2 + kx[None, :] ** 2
+    kx = 2.0 * np.pi * np.fft.rfftfreq(W)          # half spectrum of a real field
     kappa = 1.0 / xi
-    S = (kappa * kappa + k2) ** (-(nu + 1.0))
-    S /= S.mean()              # unit variance: var(ifft(fft(e) sqrt(S))) = mean(S)
-    g = np.fft.ifft2(np.fft.fft2(noise) * np.sqrt(S)).real
-    return g
+    S = (kappa * kappa + ky[:, None] ** 2 + kx[None, :] ** 2) ** (-(nu + 1.0))
+    # mean of S over the full spectrum: interior columns of the half spectrum appear twice
+    w = np.full(kx.size, 2.0)
+    w[0] = 1.0
+    if W % 2 == 0:
+        w[-1] = 1.0
+    S /= (S * w[None, :]).sum() / (H * W)           # unit variance
+    workers = min(16, os.cpu_count() or 1)
+    spec = scipy.fft.rfft2(noise, workers=workers)
+    del noise
+    spec *= np.sqrt(S)
+    del S
+    return scipy.fft.irfft2(spec, s=(H, W), workers=workers)
 
 
 def gaussian_field(H, W, nu=0.5, xi=8.0, mean=50.0, std=10.0, seed=1):

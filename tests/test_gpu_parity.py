@@ -274,3 +274,33 @@ def test_gpu_error_codes(mpr):
     ctx.run(2)
     out = ctx.predictions().cpu().numpy().reshape(4, 4)
     assert np.array_equal(out[m == 1], z[m == 1])
+
+
+def test_autotune_keeps_results(mpr):
+    """The autotuner only changes the work decomposition: the tuned context reproduces the
+    untuned one bit for bit."""
+    w = synth.workload("grid64")
+    res = []
+    for tune in (False, True):
+        ctx = _gpu_ctx(mpr, w["z"], w["mask"], seed=5, precision=mpr.FP32, n_chains=2)
+        if tune:
+            rows = ctx.autotune(4)
+            assert rows >= 2
+        ctx.infer_temperature(30)
+        ctx.run(10)
+        res.append(ctx.predictions().cpu().numpy())
+    assert np.array_equal(res[0], res[1])
+
+
+def test_large_grid_trace_matches_oracle(mpr):
+    """Inference trace on a 512 x 1000 grid: several column strips and row blocks per chain."""
+    truth, z, mask = _field(512, 1000, 9)
+    kw = dict(seed=31, n_chains=1)
+    ctx = _gpu_ctx(mpr, z, mask, **kw)
+    orc = O.Oracle(n_threads=8, **kw)
+    orc.load(z, mask)
+    Tg = ctx.infer_temperature(24)
+    To = orc.infer_temperature(24)
+    tg, to = ctx.trace(0), orc.trace(0)
+    assert np.allclose(tg, to, rtol=1e-9, atol=1e-13), np.abs(tg - to).max(axis=0)
+    assert np.allclose(Tg, To, rtol=1e-9)
