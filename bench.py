@@ -27,9 +27,9 @@ sys.path.insert(0, ROOT)
 from paper_1910_08448_amd import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-PREC = {"fp64": 0, "fp32": 1, "fp16": 2}
-BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
-DTYPE = {"fp64": "f64", "fp32": "f32", "fp16": "f16"}
+PREC = {"fp64": 0, "fp32": 1, "fp16": 2, "fix16": 3}
+BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "fix16": 2}
+DTYPE = {"fp64": "f64", "fp32": "f32", "fp16": "f32", "fix16": "f32"}   # arithmetic type of the sweep
 SWEEPS = {"grid64": (256, 100), "grid1024": (1000, 100), "grid4096": (1000, 100),
           "grid16384": (500, 50), "batch256": (1000, 100)}
 CHAINS = {"batch256": 4}

@@ -60,8 +60,9 @@ typedef enum mpr_status {
     MPR_EHIP = 6         /* HIP runtime error or a device-side time-out; context unusable */
 } mpr_status;
 
-/* storage of the spin angles (the paper's X_S, extended by 16-bit floats) */
-typedef enum mpr_precision { MPR_FP64 = 0, MPR_FP32 = 1, MPR_FP16 = 2 } mpr_precision;
+/* storage of the spin angles (the paper's X_S, extended by two 16-bit formats: IEEE half, and
+ * fixed point u = k / 32767 with a uniform resolution of 3.1e-5 of a turn) */
+typedef enum mpr_precision { MPR_FP64 = 0, MPR_FP32 = 1, MPR_FP16 = 2, MPR_FIX16 = 3 } mpr_precision;
 /* precision of the energy accumulation (X_E) and of the functions (X_F) */
 typedef enum mpr_fprec { MPR_PREC_DEFAULT = -1, MPR_PREC_DOUBLE = 0, MPR_PREC_SINGLE = 1 } mpr_fprec;
 typedef enum mpr_boundary { MPR_OPEN = 0, MPR_PERIODIC = 1 } mpr_boundary;
@@ -72,7 +73,8 @@ typedef struct mpr_config {
     int32_t precision;        /* mpr_precision: angle storage                          */
     int32_t energy_prec;      /* mpr_fprec (X_E); DEFAULT = double                     */
     int32_t func_prec;        /* mpr_fprec (X_F); DEFAULT = double for FP64 storage,
-                                 single (hardware sin/cos/exp) for FP32 and FP16      */
+                                 single (hardware sin/cos/exp) otherwise; 16-bit
+                                 storage needs single                               */
     int32_t boundary;         /* mpr_boundary; periodic needs even H and W % 4 == 0    */
     int32_t n_chains;         /* independent chains per grid, >= 1                     */
     int32_t grid_offset;      /* global index of this context's grid 0, >= 0: the Philox

@@ -93,7 +93,21 @@ __global__ __launch_bounds__(256) void k_scan(GridInfo* gi, const double* z, con
     }
     n_pred = wave_sum(n_pred);
     n_samp = wave_sum(n_samp);
-    if ((threadIdx.x & (kWave - 1)) == 0) {
+    // combine the block's waves, then one set of atomics per block
+    __shared__ uint64_t s_mn[4], s_mx[4];
+    __shared__ int64_t s_np[4], s_ns[4];
+    __shared__ int s_fl[4];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & (kWave - 1)) == 0) { s_mn[w] = mn; s_mx[w] = mx; s_np[w] = n_pred; s_ns[w] = n_samp; s_fl[w] = flags; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+            mn = s_mn[k] < mn ? s_mn[k] : mn;
+            mx = s_mx[k] > mx ? s_mx[k] : mx;
+            n_pred += s_np[k];
+            n_samp += s_ns[k];
+            flags |= s_fl[k];
+        }
         atomicMin((unsigned long long*)&G.min_ord, (unsigned long long)mn);
         atomicMax((unsigned long long*)&G.max_ord, (unsigned long long)mx);
         atomicAdd((unsigned long long*)&G.n_pred, (unsigned long long)n_pred);
@@ -131,7 +145,12 @@ __global__ __launch_bounds__(256) void k_sample_energy(GridInfo* gi, const doubl
     e_hi = wave_sum(e_hi);
     e_lo = wave_sum(e_lo);
     cnt = wave_sum(cnt);
-    if ((threadIdx.x & (kWave - 1)) == 0) {
+    __shared__ int64_t s_h[4], s_l[4], s_c[4];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & (kWave - 1)) == 0) { s_h[w] = e_hi; s_l[w] = e_lo; s_c[w] = cnt; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) { e_hi += s_h[k]; e_lo += s_l[k]; cnt += s_c[k]; }
         atomicAdd((unsigned long long*)&G.e_hi, (unsigned long long)e_hi);
         atomicAdd((unsigned long long*)&G.e_lo, (unsigned long long)e_lo);
         atomicAdd((unsigned long long*)&G.n_sample_bonds, (unsigned long long)cnt);
@@ -216,49 +235,66 @@ __global__ void k_set_base(RunCtl* run, int64_t v) { run->base_sweep = v; }
 
 // one block per (grid, chain): sum the per-item partials in item order, then move T and alpha
 template <bool ESINGLE>
-__global__ __launch_bounds__(256) void k_control(const GcDesc* gcs, GcCtl* ctl, const RunCtl* run,
-                                                 const int64_t* e_part, const int32_t* a_part,
-                                                 double* trace, int32_t sweep_off, double J,
-                                                 double acc_target, double T_min, double T_max)
+__global__ __launch_bounds__(1024) void k_control(const GcDesc* gcs, GcCtl* ctl, const RunCtl* run,
+                                                  const int64_t* e_part, const int32_t* a_part,
+                                                  double* trace, int32_t sweep_off, double J,
+                                                  double acc_target, double T_min, double T_max)
 {
-    __shared__ int64_t s_e[256], s_l[256];
-    __shared__ float s_f[256];
-    __shared__ int64_t s_a[256];
+    // one block per (grid, chain): strided sums of the item partials (four loads in flight per
+    // thread), a butterfly inside each wave, the waves in order (exact for the integer words;
+    // a fixed order for the single-precision sum)
+    __shared__ int64_t s_e[16], s_l[16], s_a[16];
+    __shared__ float s_f[16];
     const GcDesc g = gcs[blockIdx.x];
+    const int nt = (int)blockDim.x;
     int64_t e = 0, el = 0, na = 0;
     float ef = 0.0f;
-    for (int i = g.item_begin + threadIdx.x; i < g.item_end; i += blockDim.x) {
+    int i = g.item_begin + (int)threadIdx.x;
+    for (; i + 3 * nt < g.item_end; i += 4 * nt) {
+        int64_t h[4], l[4];
+        int32_t n[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            h[u] = e_part[2 * (i + u * nt)];
+            l[u] = e_part[2 * (i + u * nt) + 1];
+            n[u] = a_part[i + u * nt];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (ESINGLE) ef += __uint_as_float((uint32_t)h[u]);
+            else { e += h[u]; el += l[u]; }
+            na += n[u];
+        }
+    }
+    for (; i < g.item_end; i += nt) {
         if (ESINGLE) ef += __uint_as_float((uint32_t)e_part[2 * i]);
         else { e += e_part[2 * i]; el += e_part[2 * i + 1]; }
         na += a_part[i];
     }
-    s_e[threadIdx.x] = e;
-    s_l[threadIdx.x] = el;
-    s_f[threadIdx.x] = ef;
-    s_a[threadIdx.x] = na;
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        if (ESINGLE) ef += __shfl_xor(ef, off, kWave);
+        else { e += __shfl_xor(e, off, kWave); el += __shfl_xor(el, off, kWave); }
+        na += __shfl_xor(na, off, kWave);
+    }
+    const int w = (int)threadIdx.x >> 6;
+    if ((threadIdx.x & (kWave - 1)) == 0) { s_e[w] = e; s_l[w] = el; s_a[w] = na; s_f[w] = ef; }
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            s_e[threadIdx.x] += s_e[threadIdx.x + w];
-            s_l[threadIdx.x] += s_l[threadIdx.x + w];
-            s_f[threadIdx.x] += s_f[threadIdx.x + w];
-            s_a[threadIdx.x] += s_a[threadIdx.x + w];
-        }
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < nt / kWave; ++k) { e += s_e[k]; el += s_l[k]; na += s_a[k]; ef += s_f[k]; }
     }
     if (threadIdx.x != 0) return;
     GcCtl& c = ctl[blockIdx.x];
     const int64_t s = run->base_sweep + sweep_off;
     double e_sim, r;
-    const double A = g.n_pred > 0 ? (double)s_a[0] / (double)g.n_pred : acc_target;
+    const double A = g.n_pred > 0 ? (double)na / (double)g.n_pred : acc_target;
     if (ESINGLE) {
-        const float es = -(float)J * s_f[0] / (float)g.n_bonds;
+        const float es = -(float)J * ef / (float)g.n_bonds;
         const float num = (float)c.e_smp + (float)J, den = es + (float)J;
         float rf = den <= 1e-30f ? 2.0f : num / den;
         r = (double)rf;
         e_sim = (double)es;
     } else {
-        e_sim = -J * fix2_value(s_e[0], s_l[0]) / (double)g.n_bonds;
+        e_sim = -J * fix2_value(e, el) / (double)g.n_bonds;
         const double num = c.e_smp + J, den = e_sim + J;
         r = den <= 1e-300 ? 2.0 : num / den;
     }
@@ -416,6 +452,7 @@ struct mpr_ctx {
     int graph_k = 0;
     std::vector<int64_t> alloc_sig;                          // shapes the buffers were sized for
     int rows = 16;                                           // rows per work item
+    int ctl_threads = 64;                                    // block size of the control kernel
     int64_t item_cap = 0;                                    // items at the smallest row block
 };
 
@@ -451,10 +488,11 @@ static int check_config(const mpr_config* c)
     if (!c) return MPR_EINVAL;
     if (!(c->q > 0.0 && c->q <= 0.5)) return MPR_EINVAL;
     if (!(c->J > 0.0) || !std::isfinite(c->J)) return MPR_EINVAL;
-    if (c->precision < MPR_FP64 || c->precision > MPR_FP16) return MPR_EINVAL;
+    if (c->precision < MPR_FP64 || c->precision > MPR_FIX16) return MPR_EINVAL;
     if (c->energy_prec < -1 || c->energy_prec > 1 || c->func_prec < -1 || c->func_prec > 1)
         return MPR_EINVAL;
-    if (c->precision == MPR_FP16 && c->func_prec == MPR_PREC_DOUBLE) return MPR_EINVAL;
+    if ((c->precision == MPR_FP16 || c->precision == MPR_FIX16) && c->func_prec == MPR_PREC_DOUBLE)
+        return MPR_EINVAL;
     if (c->boundary != MPR_OPEN && c->boundary != MPR_PERIODIC) return MPR_EINVAL;
     if (c->n_chains < 1) return MPR_EINVAL;
     if (!(c->alpha0 > 0.0 && c->alpha0 <= 1.0)) return MPR_EINVAL;
@@ -525,6 +563,7 @@ static int choose_rows(const mpr_ctx* c)
 static void build_items(mpr_ctx* c, int rows)
 {
     c->items.clear();
+    int max_items = 1;
     for (size_t i = 0; i < c->gcs.size(); ++i) {
         GcDesc& d = c->gcs[i];
         d.item_begin = (int32_t)c->items.size();
@@ -532,7 +571,12 @@ static void build_items(mpr_ctx* c, int rows)
             for (int p0 = 0; p0 < d.np; p0 += kOutPairs)
                 c->items.push_back(Item{(int32_t)i, p0, y0, std::min(d.H, y0 + rows)});
         d.item_end = (int32_t)c->items.size();
+        max_items = std::max(max_items, d.item_end - d.item_begin);
     }
+    // control kernel: about 8 items per thread, 64 ... 1024 threads
+    int t = 64;
+    while (t < 1024 && t * 8 < max_items) t *= 2;
+    c->ctl_threads = t;
 }
 
 static int setup_shapes(mpr_ctx* c, int G, const int64_t* H, const int64_t* W)
@@ -637,10 +681,10 @@ static int alloc_device(mpr_ctx* c)
     return MPR_OK;
 }
 
-static dim3 site_grid(int64_t n, int ys)
+static dim3 site_grid(int64_t n, int ys, int64_t max_blocks = 4096)
 {
     int64_t b = (n + 255) / 256;
-    b = std::max<int64_t>(1, std::min<int64_t>(b, 4096));
+    b = std::max<int64_t>(1, std::min<int64_t>(b, max_blocks));
     return dim3((unsigned)b, (unsigned)ys);
 }
 
@@ -702,7 +746,7 @@ static int create_common(const mpr_config* cfg, void* stream, mpr_ctx** out)
     c->cfg = *cfg;
     c->stream = (hipStream_t)stream;
     c->sprec = cfg->precision;
-    c->elem = cfg->precision == MPR_FP64 ? 8 : (cfg->precision == MPR_FP32 ? 4 : 2);
+    c->elem = cfg->precision == MPR_FP64 ? 8 : (cfg->precision == MPR_FP32 ? 4 : 2);   // FP16, FIX16: 2
     c->fsingle = cfg->func_prec == MPR_PREC_DEFAULT ? cfg->precision != MPR_FP64
                                                     : cfg->func_prec == MPR_PREC_SINGLE;
     c->esingle = cfg->energy_prec == MPR_PREC_SINGLE;
@@ -761,7 +805,7 @@ static int load_common(mpr_ctx* c, const double* z, const uint8_t* mask)
         max_sites = std::max(max_sites, G.H * G.W);
     }
     HIPCHK(c, hipMemcpyAsync(c->d_gi, c->gi.data(), c->G * sizeof(GridInfo), hipMemcpyHostToDevice, c->stream));
-    hipLaunchKernelGGL(k_scan, site_grid(max_sites, c->G), dim3(256), 0, c->stream, c->d_gi, z, mask);
+    hipLaunchKernelGGL(k_scan, site_grid(max_sites, c->G, 256), dim3(256), 0, c->stream, c->d_gi, z, mask);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(c->gi.data(), c->d_gi, c->G * sizeof(GridInfo), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -775,12 +819,13 @@ static int load_common(mpr_ctx* c, const double* z, const uint8_t* mask)
         if (!(G.zmax > G.zmin)) return fail(c, MPR_ENOSAMPLE, "grid %d: all sample values are equal", g);
     }
     HIPCHK(c, hipMemcpyAsync(c->d_gi, c->gi.data(), c->G * sizeof(GridInfo), hipMemcpyHostToDevice, c->stream));
-    hipLaunchKernelGGL(k_sample_energy, site_grid(max_sites, c->G), dim3(256), 0, c->stream, c->d_gi,
+    hipLaunchKernelGGL(k_sample_energy, site_grid(max_sites, c->G, 256), dim3(256), 0, c->stream, c->d_gi,
                        z, mask, c->cfg.q, (int)(c->cfg.boundary == MPR_PERIODIC));
     hipLaunchKernelGGL(k_copy_z, site_grid(max_sites, c->G), dim3(256), 0, c->stream, c->d_gi, z, c->d_zcopy);
     switch (c->sprec) {
     case MPR_FP64: launch_map<double>(c, z, mask); break;
     case MPR_FP32: launch_map<float>(c, z, mask); break;
+    case MPR_FIX16: launch_map<Fix15>(c, z, mask); break;
     default: launch_map<_Float16>(c, z, mask); break;
     }
     HIPCHK(c, hipGetLastError());
@@ -844,6 +889,7 @@ static SweepFn sweep_fn(const mpr_ctx* c, int flags)
                                      : pick_sweep<double, double>(flags, c->esingle, per);
     case MPR_FP32: return c->fsingle ? pick_sweep<float, float>(flags, c->esingle, per)
                                      : pick_sweep<float, double>(flags, c->esingle, per);
+    case MPR_FIX16: return pick_sweep<Fix15, float>(flags, c->esingle, per);
     default: return pick_sweep<_Float16, float>(flags, c->esingle, per);
     }
 }
@@ -877,7 +923,7 @@ static void enqueue_sweep(mpr_ctx* c, int flags, int sweep_off, int src_buf, con
 static void enqueue_control(mpr_ctx* c, int sweep_off)
 {
     auto fn = c->esingle ? k_control<true> : k_control<false>;
-    hipLaunchKernelGGL(fn, dim3((unsigned)c->gcs.size()), dim3(256), 0, c->stream, c->d_gcs, c->d_ctl,
+    hipLaunchKernelGGL(fn, dim3((unsigned)c->gcs.size()), dim3(c->ctl_threads), 0, c->stream, c->d_gcs, c->d_ctl,
                        c->d_run, c->d_e_part, c->d_a_part, c->d_trace, sweep_off, c->cfg.J,
                        c->cfg.acc_target, c->cfg.T_min, c->cfg.T_max);
 }
@@ -1008,6 +1054,7 @@ int mpr_get_predictions(mpr_ctx* c, double* zhat)
     switch (c->sprec) {
     case MPR_FP64: hipLaunchKernelGGL(k_finalize<double>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_gi, c->d_state[c->cur], c->d_acc, c->d_zcopy, zhat, c->C, c->n_avg); break;
     case MPR_FP32: hipLaunchKernelGGL(k_finalize<float>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_gi, c->d_state[c->cur], c->d_acc, c->d_zcopy, zhat, c->C, c->n_avg); break;
+    case MPR_FIX16: hipLaunchKernelGGL(k_finalize<Fix15>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_gi, c->d_state[c->cur], c->d_acc, c->d_zcopy, zhat, c->C, c->n_avg); break;
     default: hipLaunchKernelGGL(k_finalize<_Float16>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_gi, c->d_state[c->cur], c->d_acc, c->d_zcopy, zhat, c->C, c->n_avg); break;
     }
     HIPCHK(c, hipGetLastError());
@@ -1066,6 +1113,7 @@ int mpr_get_state(mpr_ctx* c, double* u, double* acc, double* ctl_host, int64_t*
         switch (c->sprec) {
         case MPR_FP64: launch_get_state<double>(c, u, acc, gc_grid(c)); break;
         case MPR_FP32: launch_get_state<float>(c, u, acc, gc_grid(c)); break;
+        case MPR_FIX16: launch_get_state<Fix15>(c, u, acc, gc_grid(c)); break;
         default: launch_get_state<_Float16>(c, u, acc, gc_grid(c)); break;
         }
         HIPCHK(c, hipGetLastError());
@@ -1098,6 +1146,7 @@ int mpr_set_state(mpr_ctx* c, const double* u, const double* acc, const double* 
         switch (c->sprec) {
         case MPR_FP64: launch_set_state<double>(c, u, nullptr, 0, gc_grid(c)); break;
         case MPR_FP32: launch_set_state<float>(c, u, nullptr, 0, gc_grid(c)); break;
+        case MPR_FIX16: launch_set_state<Fix15>(c, u, nullptr, 0, gc_grid(c)); break;
         default: launch_set_state<_Float16>(c, u, nullptr, 0, gc_grid(c)); break;
         }
         int flag = 0;
@@ -1109,6 +1158,7 @@ int mpr_set_state(mpr_ctx* c, const double* u, const double* acc, const double* 
         switch (c->sprec) {
         case MPR_FP64: launch_set_state<double>(c, u, acc, 1, gc_grid(c)); break;
         case MPR_FP32: launch_set_state<float>(c, u, acc, 1, gc_grid(c)); break;
+        case MPR_FIX16: launch_set_state<Fix15>(c, u, acc, 1, gc_grid(c)); break;
         default: launch_set_state<_Float16>(c, u, acc, 1, gc_grid(c)); break;
         }
         HIPCHK(c, hipGetLastError());

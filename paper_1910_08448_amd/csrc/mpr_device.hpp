@@ -228,6 +228,35 @@ template <> struct Store<_Float16> {
     template <class F> static __device__ __forceinline__ F round(F u) { return (F)(float)(_Float16)(float)u; }
 };
 
+// 16-bit fixed point: 15 fraction bits with u = k / 32767 (uniform resolution 3.1e-5 of a turn,
+// against FP16's 2^-11 just below 1) and the sample flag in bit 15.
+struct Fix15 {};
+
+template <> struct Store<Fix15> {
+    using raw = uint16_t;
+    struct pair { raw a, b; };
+    static __device__ __forceinline__ pair load(const void* base, int idx)
+    {
+        const uint32_t v = *((const uint32_t*)((const uint16_t*)base + idx));
+        return {(raw)(v & 0xffffu), (raw)(v >> 16)};
+    }
+    static __device__ __forceinline__ void store(void* base, int idx, pair p)
+    {
+        *((uint32_t*)((uint16_t*)base + idx)) = (uint32_t)p.a | ((uint32_t)p.b << 16);
+    }
+    static __device__ __forceinline__ bool sample(raw r) { return (r >> 15) != 0; }
+    template <class F> static __device__ __forceinline__ F value(raw r)
+    {
+        return (F)(r & 0x7fffu) * (F)(1.0 / 32767.0);
+    }
+    template <class F> static __device__ __forceinline__ raw encode(F u)
+    {
+        const F k = __builtin_rint(u * (F)32767.0);
+        return (raw)(k < (F)0 ? (F)0 : (k > (F)32767 ? (F)32767 : k));
+    }
+    template <class F> static __device__ __forceinline__ F round(F u) { return value<F>(encode<F>(u)); }
+};
+
 // ------------------------------------------------------------------ per-site hybrid update
 // Input: current angle u (storage-rounded), local field (C, S) = sum_j (cos, sin)(2 pi q u_j),
 // uniforms.  Output: new angle (storage-rounded), its (cos, sin)(2 pi q u), decision bits.

@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libmpr.so")
 
 OK, EINVAL, ENOSAMPLE, EBIPARTITE, ESTATE, ENOMEM, EHIP = range(7)
-FP64, FP32, FP16 = 0, 1, 2
+FP64, FP32, FP16, FIX16 = 0, 1, 2, 3
 PREC_DEFAULT, PREC_DOUBLE, PREC_SINGLE = -1, 0, 1
 OPEN, PERIODIC = 0, 1
 DEC_OR, DEC_ACCEPT, DEC_OUTSIDE = 1, 2, 4

@@ -304,3 +304,46 @@ def test_large_grid_trace_matches_oracle(mpr):
     tg, to = ctx.trace(0), orc.trace(0)
     assert np.allclose(tg, to, rtol=1e-9, atol=1e-13), np.abs(tg - to).max(axis=0)
     assert np.allclose(Tg, To, rtol=1e-9)
+
+
+SETTINGS = {  # the paper's X_S X_E X_F (Sec. 2): spins, energy, functions in D(ouble) or S(ingle)
+    "DDD": (0, 0, 0), "DSD": (0, 1, 0), "DDS": (0, 0, 1), "SDD": (1, 0, 0),
+    "SDS": (1, 0, 1), "DSS": (0, 1, 1), "SSD": (1, 1, 0), "SSS": (1, 1, 1),
+    "H-DS (FP16 spins)": (2, 0, 1), "F-DS (16-bit fixed-point spins)": (3, 0, 1),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SETTINGS))
+def test_precision_settings(mpr, name):
+    """Every precision setting: decisions from an identical state agree with the FP64 oracle
+    (>= 99.99 % with double functions, >= 99 % otherwise) and the prediction MAE against the
+    truth stays within 1 % of the oracle's (the paper finds Delta MAAE ~ 1e-4 %, Sec. 3)."""
+    prec, eprec, fprec = SETTINGS[name]
+    kw = dict(precision=prec, energy_prec=eprec, func_prec=fprec)
+    # decisions
+    truth, z, mask = _field(48, 80, 123)
+    ctx = _gpu_ctx(mpr, z, mask, seed=7, alpha0=0.4, **kw)
+    orc = O.Oracle(n_threads=2, seed=7, alpha0=0.4)
+    orc.load(z, mask)
+    u0 = synth.random_state(1, mask, 8)
+    ctx.set_state(u=_dev(u0.reshape(-1), torch.float64))
+    orc.set_state(phi=TWO_PI * u0)
+    ctx.set_temperature(0.08)
+    orc.set_temperature(0.08)
+    dg = ctx.debug_sweep(3).cpu().numpy().reshape(1, 48, 80)
+    do = orc.debug_sweep(3)
+    free = np.broadcast_to(mask == 0, dg.shape)
+    agree = (dg == do)[free].mean()
+    assert agree >= (0.9999 if fprec == 0 else 0.99), agree
+    # predictions
+    w = synth.workload("grid64")
+    m = w["mask"] == 0
+    kwo = dict(seed=w["mc_seed"], n_chains=4)
+    zo, _ = O.predict(w["z"], w["mask"], 256, 100, n_threads=4, **kwo)
+    ctx = _gpu_ctx(mpr, w["z"], w["mask"], **kwo, **kw)
+    ctx.infer_temperature(256)
+    ctx.run(100)
+    zg = ctx.predictions().cpu().numpy().reshape(64, 64)
+    mae_o = np.abs(zo - w["truth"])[m].mean()
+    mae_g = np.abs(zg - w["truth"])[m].mean()
+    assert abs(mae_g / mae_o - 1) <= 0.01, (mae_g, mae_o)

@@ -47,7 +47,8 @@ def test_defaults_and_host_validation(M):
     h = ctypes.c_void_p()
     for kw in [dict(q=0.0), dict(q=0.51), dict(J=0.0), dict(n_chains=0), dict(alpha0=1.5),
                dict(acc_target=0.0), dict(T_min=0.0), dict(T_min=2.0, T_max=1.0),
-               dict(precision=3), dict(func_prec=5), dict(precision=M.FP16, func_prec=M.PREC_DOUBLE),
+               dict(precision=4), dict(func_prec=5), dict(precision=M.FP16, func_prec=M.PREC_DOUBLE),
+               dict(precision=M.FIX16, func_prec=M.PREC_DOUBLE),
                dict(grid_offset=-1), dict(tile_rows=-2)]:
         bad = M.default_config(**kw)
         assert M.mpr_create(ctypes.byref(bad), None, ctypes.byref(h)) == M.EINVAL, kw
