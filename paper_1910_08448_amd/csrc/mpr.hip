@@ -544,12 +544,19 @@ static const int kRowCandidates[] = {2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24
 static int choose_rows(const mpr_ctx* c)
 {
     if (c->cfg.tile_rows > 0) return c->cfg.tile_rows;
-    // large workloads: 64-row items keep >= 16 waves per SIMD in flight (measured best on
-    // 16384^2); small ones: the round model above
-    if (count_items(c, 64) >= 16 * 1024) return 64;
+    // Measured on MI355X: more waves in flight beat longer items until ~32 waves per SIMD
+    // (16384^2: 32 rows best), then halo rows cost more than they hide; mid-size grids want
+    // >= 4 waves per SIMD (4096^2: 16 rows); grids too small for that use the round model.
     int maxH = 0;
     for (int g = 0; g < c->G; ++g) maxH = std::max<int>(maxH, (int)c->H[g]);
-    int best = 4;
+    int best = 0;
+    for (int r : kRowCandidates)
+        if (r >= 16 && r <= maxH && count_items(c, r) >= 32 * 1024) best = r;
+    if (best) return best;
+    for (int r : kRowCandidates)
+        if (r >= 4 && r <= maxH && count_items(c, r) >= 4 * 1024) best = r;
+    if (best) return best;
+    best = 4;
     double best_cost = 1e300;
     for (int r : kRowCandidates) {
         if (r > maxH && r > 2) break;

@@ -388,8 +388,10 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
     const int col = 2 * jj;                              // plane column of member 0
     const int plane_sz = H * pitch;                      // < 2^30 (checked on the host)
 
-    const S* __restrict__ src = (const S*)a.src + g.plane_off;
-    S* __restrict__ dst = (S*)a.dst + g.plane_off;
+    // offsets count stored elements (the tag type of a fixed-point storage has no size of its own)
+    using Raw = typename St::raw;
+    const Raw* __restrict__ src = (const Raw*)a.src + g.plane_off;
+    Raw* __restrict__ dst = (Raw*)a.dst + g.plane_off;
 
     auto row_ok = [&](int y) -> bool { return PER | ((y >= 0) & (y < H)); };
     auto wrap = [&](int y) -> int { return PER ? (y < 0 ? y + H : (y >= H ? y - H : y)) : y; };
@@ -469,36 +471,44 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
 
     const int ya = it.y0, yb = it.y1;
     const RowCS<F> zero = {(F)0, (F)0, (F)0, (F)0};
-    // 3-row windows (colour-1 old rows k-1, k, k+1; colour-0 new rows k-2, k-1, k) live in
-    // slots A, B, C whose roles rotate with k, so the unrolled loop moves no registers
-    RowCS<F> w1A, w1B, w1C;       // colour-1 old (cos, sin)
-    Pair v1A, v1B, v1C;           // colour-1 old raw values
-    RowCS<F> w0A = zero, w0B = zero, w0C = zero;   // colour-0 new (cos, sin)
-    Pair v0_next, n0_prev = Pair{0, 0};
-    int d0_prev_a = 0, d0_prev_b = 0;
+    // window: colour-1 old rows k-1, k, k+1; colour-0 new rows k-2, k-1, k
+    Pair v0_cur, v0_next, v1_m1, v1_0, v1_p1;
+    RowCS<F> w1_m1, w1_0, w1_p1;
+    RowCS<F> w0_m2, w0_m1, w0_0;
+    Pair n0_m1, n0_0;
+    int d0_m1a = 0, d0_m1b = 0, d0_0a = 0, d0_0b = 0;
 
-    v1A = load_pair(1, ya - 2);
-    w1A = cs_of(v1A, ya - 2, 1);
-    v1B = load_pair(1, ya - 1);
-    w1B = cs_of(v1B, ya - 1, 1);
+    v1_0 = load_pair(1, ya - 2);
+    w1_0 = cs_of(v1_0, ya - 2, 1);
+    v1_p1 = load_pair(1, ya - 1);
+    w1_p1 = cs_of(v1_p1, ya - 1, 1);
     v0_next = load_pair(0, ya - 1);
+    w0_m1 = zero;
+    w0_0 = zero;
+    n0_0 = Pair{0, 0};
+    // loads run one row ahead of their use, so their latency overlaps a row of arithmetic
+    Pair pf1 = load_pair(1, ya), pf0 = load_pair(0, ya);
 
     // iteration k: load row k+1, colour-0 update of row k, colour-1 update and store of row k-1
-    auto step = [&](int k, const RowCS<F>& w1m, const RowCS<F>& w1z, RowCS<F>& w1p,
-                    const Pair& v1m, Pair& v1p, const RowCS<F>& w0m2, const RowCS<F>& w0m1,
-                    RowCS<F>& w0z) {
-        const Pair v0_cur = v0_next;
-        v1p = load_pair(1, k + 1);
-        v0_next = load_pair(0, k + 1);
-        w1p = cs_of(v1p, k + 1, 1);
-        Pair n0;
-        int d0a = 0, d0b = 0;
+    for (int k = ya - 1; k <= yb; ++k) {
+        w1_m1 = w1_0; w1_0 = w1_p1;
+        v1_m1 = v1_0; v1_0 = v1_p1;
+        w0_m2 = w0_m1; w0_m1 = w0_0;
+        n0_m1 = n0_0;
+        d0_m1a = d0_0a; d0_m1b = d0_0b;
+        v0_cur = v0_next;
+        v1_p1 = pf1;
+        v0_next = pf0;
+        pf1 = load_pair(1, k + 2);
+        pf0 = load_pair(0, k + 2);
+        w1_p1 = cs_of(v1_p1, k + 1, 1);
         if (row_ok(k)) {
             F e_unused;
-            update_row(v0_cur, w1m, w1z, w1p, k, 0, n0, w0z, d0a, d0b, e_unused);
+            update_row(v0_cur, w1_m1, w1_0, w1_p1, k, 0, n0_0, w0_0, d0_0a, d0_0b, e_unused);
         } else {
-            n0 = v0_cur;
-            w0z = zero;
+            n0_0 = v0_cur;
+            w0_0 = zero;
+            d0_0a = d0_0b = 0;
         }
         const int y = k - 1;
         if (y >= ya) {
@@ -506,26 +516,26 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
             RowCS<F> cs1;
             int d1a, d1b;
             F e;
-            update_row(v1m, w0m2, w0m1, w0z, y, 1, n1, cs1, d1a, d1b, e);
+            update_row(v1_m1, w0_m2, w0_m1, w0_0, y, 1, n1, cs1, d1a, d1b, e);
             if (out_lane) {
                 const int r0 = y * pitch + col;
-                St::store(dst, r0, n0_prev);
+                St::store(dst, r0, n0_m1);
                 St::store(dst, plane_sz + r0, n1);
-                n_acc += ((d0_prev_a >> 1) & 1) + ((d0_prev_b >> 1) & 1) + ((d1a >> 1) & 1) + ((d1b >> 1) & 1);
+                n_acc += ((d0_m1a >> 1) & 1) + ((d0_m1b >> 1) & 1) + ((d1a >> 1) & 1) + ((d1b >> 1) & 1);
                 if (FLAGS & F_ENERGY) {
                     if (ESINGLE) e_flt += (float)e;
                     else { const Fix2 f = fixed64x2((double)e); e_hi += f.hi; e_lo += f.lo; }
                 }
                 if (FLAGS & F_ACC) {
-                    const bool f0a = exists(y, 0, 0) & !St::sample(n0_prev.a);
-                    const bool f0b = exists(y, 0, 1) & !St::sample(n0_prev.b);
+                    const bool f0a = exists(y, 0, 0) & !St::sample(n0_m1.a);
+                    const bool f0b = exists(y, 0, 1) & !St::sample(n0_m1.b);
                     const bool f1a = exists(y, 1, 0) & !St::sample(n1.a);
                     const bool f1b = exists(y, 1, 1) & !St::sample(n1.b);
                     double* acc = a.acc + g.plane_off;
                     double2 p0 = *((double2*)(acc + r0));
                     double2 p1 = *((double2*)(acc + plane_sz + r0));
-                    if (f0a) p0.x += St::template value<double>(n0_prev.a);
-                    if (f0b) p0.y += St::template value<double>(n0_prev.b);
+                    if (f0a) p0.x += St::template value<double>(n0_m1.a);
+                    if (f0b) p0.y += St::template value<double>(n0_m1.b);
                     if (f1a) p1.x += St::template value<double>(n1.a);
                     if (f1b) p1.y += St::template value<double>(n1.b);
                     *((double2*)(acc + r0)) = p0;
@@ -535,28 +545,15 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
                     uint8_t* d = a.dec + g.site_off + (int64_t)y * g.W;
                     const int xb = 4 * jj;
                     const int o0 = y & 1, o1 = (y + 1) & 1;
-                    if (exists(y, 0, 0)) d[xb + o0] = (uint8_t)d0_prev_a;
-                    if (exists(y, 0, 1)) d[xb + 2 + o0] = (uint8_t)d0_prev_b;
+                    if (exists(y, 0, 0)) d[xb + o0] = (uint8_t)d0_m1a;
+                    if (exists(y, 0, 1)) d[xb + 2 + o0] = (uint8_t)d0_m1b;
                     if (exists(y, 1, 0)) d[xb + o1] = (uint8_t)d1a;
                     if (exists(y, 1, 1)) d[xb + 2 + o1] = (uint8_t)d1b;
                 }
             }
         }
-        n0_prev = n0;
-        d0_prev_a = d0a;
-        d0_prev_b = d0b;
-    };
-
-    // roles (k-1, k, k+1) of the colour-1 slots and (k-2, k-1, k) of the colour-0 slots
-    // cycle A B C -> B C A -> C A B
-    for (int k = ya - 1; k <= yb;) {
-        step(k, w1A, w1B, w1C, v1A, v1C, w0A, w0B, w0C);
-        if (++k > yb) break;
-        step(k, w1B, w1C, w1A, v1B, v1A, w0B, w0C, w0A);
-        if (++k > yb) break;
-        step(k, w1C, w1A, w1B, v1C, v1B, w0C, w0A, w0B);
-        ++k;
     }
+
     // wave reductions -> per-item partials (exact integers, or a fixed-order float tree)
     for (int off = kWave / 2; off > 0; off >>= 1) {
         n_acc += __shfl_xor(n_acc, off, kWave);
