@@ -48,13 +48,6 @@ double order_inverse(uint64_t o)
     return d;
 }
 
-// value of a two-word fixed-point sum hi 2^-32 + lo 2^-64 (hi split so no bit is lost)
-__host__ __device__ inline double fix2_value(int64_t hi, int64_t lo)
-{
-    const int64_t hi_top = hi >> 20, hi_bot = hi - (hi_top << 20);
-    return (double)hi_top * 1048576.0 / kTwoPow32 +
-           ((double)hi_bot / kTwoPow32 + (double)lo / (kTwoPow32 * kTwoPow32));
-}
 
 template <class T> __device__ __forceinline__ T wave_sum(T v)
 {
@@ -208,11 +201,15 @@ __global__ __launch_bounds__(256) void k_copy_z(const GridInfo* gi, const double
 }
 
 // ------------------------------------------------------------------ control kernels
-__global__ void k_infer_begin(GcCtl* ctl, int n_gc, double J, double T_min, double T_max,
-                              RunCtl* run, int64_t s_half, int64_t trace_base, int64_t trace_cap)
+__global__ void k_infer_begin(GcCtl* ctl, GcCtl* ictl, int64_t* gacc, int n_gc, double J,
+                              double T_min, double T_max, RunCtl* run, int64_t s_half,
+                              int64_t trace_base, int64_t trace_cap, int64_t n_infer)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) { run->s_half = s_half; run->trace_base = trace_base; run->trace_cap = trace_cap; }
+    if (i == 0) {
+        run->s_half = s_half; run->trace_base = trace_base; run->trace_cap = trace_cap;
+        run->n_infer = n_infer;
+    }
     if (i >= n_gc) return;
     GcCtl& c = ctl[i];
     const double T0 = fmin(fmax(4.0 * (c.e_smp + J), T_min), T_max);
@@ -220,14 +217,37 @@ __global__ void k_infer_begin(GcCtl* ctl, int n_gc, double J, double T_min, doub
     c.T = T0;
     c.T_sum = 0.0;
     c.T_cnt = 0;
+    ictl[i] = c;                                   // state of inference sweep 0
+    for (int slot = 0; slot < 3; ++slot)
+        for (int k = 0; k < kAccPerGc; ++k) gacc[((int64_t)slot * n_gc + i) * kAccPerGc + k] = 0;
 }
 
-__global__ void k_infer_end(GcCtl* ctl, int n_gc)
+// after n inference sweeps: with in-sweep control (double-precision energy) apply the control
+// step of the last sweep and copy the state out; then T-hat = mean of the recorded temperatures
+__global__ void k_infer_end(const GcDesc* gcs, GcCtl* ctl, const GcCtl* ictl, const int64_t* gacc,
+                            double* trace, const RunCtl* run, int n_gc, int fused, int64_t n,
+                            double J, double acc_target, double T_min, double T_max)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_gc) return;
-    GcCtl& c = ctl[i];
+    GcCtl c = ctl[i];
+    if (fused && n > 0) {
+        const int t = (int)(n - 1);
+        c = ictl[(t & 1) * n_gc + i];
+        const int64_t* A = gacc + ((int64_t)(t % 3) * n_gc + i) * kAccPerGc;
+        int64_t eh = 0, el = 0, na = 0;
+        for (int k = 0; k < kAccCopies; ++k) {
+            eh += A[k * kAccWords];
+            el += A[k * kAccWords + 1];
+            na += A[k * kAccWords + 2];
+        }
+        const GcDesc g = gcs[i];
+        control_step(c, -J * fix2_value(eh, el) / (double)g.n_bonds, na, g.n_pred,
+                     run->trace_base + t >= run->s_half, J, acc_target, T_min, T_max, 0.0, false,
+                     trace + ((int64_t)i * run->trace_cap + t) * 4);
+    }
     c.T = c.T_cnt > 0 ? c.T_sum / (double)c.T_cnt : c.T0;
+    ctl[i] = c;
 }
 
 __global__ void k_advance(RunCtl* run, int64_t n) { run->base_sweep += n; }
@@ -283,32 +303,22 @@ __global__ __launch_bounds__(1024) void k_control(const GcDesc* gcs, GcCtl* ctl,
         for (int k = 1; k < nt / kWave; ++k) { e += s_e[k]; el += s_l[k]; na += s_a[k]; ef += s_f[k]; }
     }
     if (threadIdx.x != 0) return;
-    GcCtl& c = ctl[blockIdx.x];
+    GcCtl c = ctl[blockIdx.x];
     const int64_t s = run->base_sweep + sweep_off;
-    double e_sim, r;
-    const double A = g.n_pred > 0 ? (double)na / (double)g.n_pred : acc_target;
+    double e_sim, r_single = 0.0;
     if (ESINGLE) {
         const float es = -(float)J * ef / (float)g.n_bonds;
         const float num = (float)c.e_smp + (float)J, den = es + (float)J;
-        float rf = den <= 1e-30f ? 2.0f : num / den;
-        r = (double)rf;
+        r_single = (double)(den <= 1e-30f ? 2.0f : num / den);
         e_sim = (double)es;
     } else {
         e_sim = -J * fix2_value(e, el) / (double)g.n_bonds;
-        const double num = c.e_smp + J, den = e_sim + J;
-        r = den <= 1e-300 ? 2.0 : num / den;
     }
     const int64_t t = s - run->trace_base;
-    if (t >= 0 && t < run->trace_cap) {
-        double* tr = trace + ((int64_t)blockIdx.x * run->trace_cap + t) * 4;
-        tr[0] = e_sim; tr[1] = c.T; tr[2] = c.alpha; tr[3] = A;
-    }
-    if (s >= run->s_half) { c.T_sum += c.T; c.T_cnt += 1; }
-    r = fmin(fmax(r, 0.5), 2.0);
-    c.T = fmin(fmax(c.T * r, T_min), T_max);
-    c.alpha = fmin(fmax(c.alpha * A / acc_target, 1e-3), 1.0);
-    c.e_sim = e_sim;
-    c.acc_rate = A;
+    double* tr = (t >= 0 && t < run->trace_cap) ? trace + ((int64_t)blockIdx.x * run->trace_cap + t) * 4 : nullptr;
+    control_step(c, e_sim, na, g.n_pred, s >= run->s_half, J, acc_target, T_min, T_max, r_single,
+                 ESINGLE, tr);
+    ctl[blockIdx.x] = c;
 }
 
 // ------------------------------------------------------------------ finalise / checkpoint
@@ -432,6 +442,8 @@ struct mpr_ctx {
     GcDesc* d_gcs = nullptr;
     Item* d_items = nullptr;
     GcCtl* d_ctl = nullptr;
+    GcCtl* d_ictl = nullptr;     // [2][n_gc] control states during an inference
+    int64_t* d_gacc = nullptr;   // [3][n_gc][kAccPerGc] inference accumulators
     RunCtl* d_run = nullptr;
     RunCtl* d_dbg_run = nullptr;
     GridInfo* d_gi = nullptr;
@@ -508,13 +520,13 @@ static void free_device(mpr_ctx* c)
     c->graphs.clear();
     void* ptrs[] = {c->d_gcs, c->d_items, c->d_ctl, c->d_run, c->d_dbg_run, c->d_gi,
                     c->d_state[0], c->d_state[1], c->d_acc, c->d_zcopy, c->d_e_part,
-                    c->d_a_part, c->d_trace, c->d_flag};
+                    c->d_a_part, c->d_trace, c->d_flag, c->d_ictl, c->d_gacc};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     c->d_gcs = nullptr; c->d_items = nullptr; c->d_ctl = nullptr; c->d_run = nullptr;
     c->d_dbg_run = nullptr; c->d_gi = nullptr; c->d_state[0] = c->d_state[1] = nullptr;
     c->d_acc = nullptr; c->d_zcopy = nullptr; c->d_e_part = nullptr; c->d_a_part = nullptr;
-    c->d_trace = nullptr; c->d_flag = nullptr;
+    c->d_trace = nullptr; c->d_flag = nullptr; c->d_ictl = nullptr; c->d_gacc = nullptr;
     c->trace_cap = 0;
     c->alloc_sig.clear();
 }
@@ -671,6 +683,8 @@ static int alloc_device(mpr_ctx* c)
     HIPCHK(c, hipMalloc(&c->d_gcs, n_gc * sizeof(GcDesc)));
     HIPCHK(c, hipMalloc(&c->d_items, c->item_cap * sizeof(Item)));
     HIPCHK(c, hipMalloc(&c->d_ctl, n_gc * sizeof(GcCtl)));
+    HIPCHK(c, hipMalloc(&c->d_ictl, 2 * n_gc * sizeof(GcCtl)));
+    HIPCHK(c, hipMalloc(&c->d_gacc, 3 * n_gc * kAccPerGc * sizeof(int64_t)));
     HIPCHK(c, hipMalloc(&c->d_run, sizeof(RunCtl)));
     HIPCHK(c, hipMalloc(&c->d_dbg_run, sizeof(RunCtl)));
     HIPCHK(c, hipMalloc(&c->d_gi, c->G * sizeof(GridInfo)));
@@ -915,6 +929,13 @@ static void enqueue_sweep(mpr_ctx* c, int flags, int sweep_off, int src_buf, con
     a.dec = dec;
     a.e_part = c->d_e_part;
     a.a_part = c->d_a_part;
+    a.ictl = c->d_ictl;
+    a.gacc = c->d_gacc;
+    a.trace = c->d_trace;
+    a.acc_target = c->cfg.acc_target;
+    a.T_min = c->cfg.T_min;
+    a.T_max = c->cfg.T_max;
+    a.n_gc = (int32_t)c->gcs.size();
     a.n_items = (int32_t)c->items.size();
     a.sweep_off = sweep_off;
     a.key0 = (uint32_t)(c->cfg.seed & 0xffffffffu);
@@ -942,7 +963,7 @@ static void enqueue_block(mpr_ctx* c, int mode, int n)
     int buf = c->cur;
     for (int i = 0; i < n; ++i) {
         enqueue_sweep(c, flags, i, buf, c->d_run, nullptr);
-        if (mode == MODE_EQUIL) enqueue_control(c, i);
+        if (mode == MODE_EQUIL && c->esingle) enqueue_control(c, i);   // else inside the sweeps
         buf ^= 1;
     }
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, c->stream, c->d_run, (int64_t)n);
@@ -993,12 +1014,14 @@ int mpr_infer_temperature(mpr_ctx* c, int32_t n_equil, double* T_host)
         c->graphs.clear();
     }
     hipLaunchKernelGGL(k_infer_begin, dim3((n_gc + 255) / 256), dim3(256), 0, c->stream, c->d_ctl,
-                       n_gc, c->cfg.J, c->cfg.T_min, c->cfg.T_max, c->d_run,
+                       c->d_ictl, c->d_gacc, n_gc, c->cfg.J, c->cfg.T_min, c->cfg.T_max, c->d_run,
                        (int64_t)(c->next_sweep + n_equil / 2), (int64_t)c->next_sweep,
-                       (int64_t)c->trace_cap);
+                       (int64_t)c->trace_cap, (int64_t)n_equil);
     rc = run_sweeps(c, MODE_EQUIL, n_equil);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_infer_end, dim3((n_gc + 255) / 256), dim3(256), 0, c->stream, c->d_ctl, n_gc);
+    hipLaunchKernelGGL(k_infer_end, dim3((n_gc + 255) / 256), dim3(256), 0, c->stream, c->d_gcs,
+                       c->d_ctl, c->d_ictl, c->d_gacc, c->d_trace, c->d_run, n_gc, (int)!c->esingle,
+                       (int64_t)n_equil, c->cfg.J, c->cfg.acc_target, c->cfg.T_min, c->cfg.T_max);
     HIPCHK(c, hipGetLastError());
     c->trace_len = n_equil;
     c->phase = std::max(c->phase, (int)PH_TEMPERED);

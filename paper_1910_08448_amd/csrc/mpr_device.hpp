@@ -47,9 +47,21 @@ struct GcCtl {             // per (grid, chain) control state, device resident
 struct RunCtl {            // per context, device resident
     int64_t base_sweep;    // Philox sweep index of sweep offset 0 of the next graph replay
     int64_t s_half;        // first sweep whose temperature enters the estimate
-    int64_t trace_base;    // sweep index of trace entry 0
+    int64_t trace_base;    // sweep index of trace entry 0 = first sweep of the inference
     int64_t trace_cap;     // trace entries per (grid, chain)
+    int64_t n_infer;       // sweeps of the current inference: [trace_base, trace_base + n_infer)
 };
+
+// Inference sweeps in double-precision energy carry their own temperature control: sweep t of
+// an inference adds its exact integer sums (energy words, accepted moves) into slot t % 3 of the
+// per-(grid, chain) accumulators (kAccCopies copies, one per XCD-interleaved block class, to
+// spread the atomics), and every wave of sweep t > 0 first applies the control step of sweep
+// t - 1 from slot (t - 1) % 3 and the control state in slot (t - 1) & 1.  The first item of
+// each (grid, chain) stores the new state in slot t & 1, the trace entry of sweep t - 1, and
+// clears slot (t + 1) % 3 for the next sweep.  Kernel boundaries order all of it.
+constexpr int kAccCopies = 8;
+constexpr int kAccWords = 4;       // energy high word, energy low word, accepted moves, unused
+constexpr int kAccPerGc = kAccCopies * kAccWords;
 
 enum { F_ENERGY = 1, F_ACC = 2, F_DEC = 4 };
 enum { DEC_OR = 1, DEC_ACCEPT = 2, DEC_OUTSIDE = 4 };
@@ -69,6 +81,11 @@ struct SweepArgs {
     uint8_t* dec;
     int64_t* e_part;           // per item: energy partial [2] (two-word fixed point, or float bits)
     int32_t* a_part;           // per item: accepted moves
+    GcCtl* ictl;               // inference control states [2][n_gc]
+    int64_t* gacc;             // inference accumulators [3][n_gc][kAccPerGc]
+    double* trace;             // [n_gc][trace_cap][4]
+    double acc_target, T_min, T_max;
+    int32_t n_gc;
     int32_t n_items;
     int32_t sweep_off;         // sweep index = run->base_sweep + sweep_off
     uint32_t key0, key1;
@@ -326,6 +343,39 @@ __device__ __forceinline__ Fix2 fixed64x2(double e)
     return Fix2{a, round_to_i64(r)};
 }
 
+// value of a two-word fixed-point sum hi 2^-32 + lo 2^-64 (hi split so every product is exact)
+__host__ __device__ inline double fix2_value(int64_t hi, int64_t lo)
+{
+    const double k32 = 4294967296.0;
+    const int64_t hi_top = hi >> 20, hi_bot = hi - (hi_top << 20);
+    return (double)hi_top * 1048576.0 / k32 + ((double)hi_bot / k32 + (double)lo / (k32 * k32));
+}
+
+// One step of the temperature and window control after an inference sweep (the multiplicative
+// energy matching and the acceptance-driven window): e_sim from the exact bond-energy sum, T
+// moved by the clamped ratio (e_smp + J) / (e_sim + J), alpha by A / A_target.  `c` holds the
+// state used by the sweep and becomes the state of the next one; tr (if not null) receives the
+// sweep's trace entry (e_sim, T, alpha, A).
+__device__ inline void control_step(GcCtl& c, double e_sim, int64_t n_acc, int64_t n_pred,
+                                    bool second_half, double J, double acc_target, double T_min,
+                                    double T_max, double r_single, bool use_single, double* tr)
+{
+    const double A = n_pred > 0 ? (double)n_acc / (double)n_pred : acc_target;
+    double r;
+    if (use_single) r = r_single;
+    else {
+        const double num = c.e_smp + J, den = e_sim + J;
+        r = den <= 1e-300 ? 2.0 : num / den;
+    }
+    if (tr) { tr[0] = e_sim; tr[1] = c.T; tr[2] = c.alpha; tr[3] = A; }
+    if (second_half) { c.T_sum += c.T; c.T_cnt += 1; }
+    r = fmin(fmax(r, 0.5), 2.0);
+    c.T = fmin(fmax(c.T * r, T_min), T_max);
+    c.alpha = fmin(fmax(c.alpha * A / acc_target, 1e-3), 1.0);
+    c.e_sim = e_sim;
+    c.acc_rate = A;
+}
+
 // ------------------------------------------------------------------ cross-lane shifts
 // DPP wave shifts by one lane (a plain VALU move, no LDS crossbar): from_left(v) gives lane i
 // the value of lane i-1, from_right(v) the value of lane i+1; lanes without a source get 0.
@@ -367,8 +417,44 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
     if (wid >= a.n_items) return;                 // whole waves leave together
     const Item it = a.items[wid];
     const GcDesc g = a.gcs[it.gc];
-    const GcCtl ctl = a.ctl[it.gc];
-    const uint32_t sweep = (uint32_t)(a.run->base_sweep + a.sweep_off);
+    const int64_t s_abs = a.run->base_sweep + a.sweep_off;
+    const uint32_t sweep = (uint32_t)s_abs;
+
+    // control state of this sweep: frozen, or (inference in double-precision energy) the
+    // previous sweep's control step applied here from its exact sums
+    constexpr bool FUSED = (FLAGS & F_ENERGY) && !ESINGLE;
+    GcCtl ctl;
+    int acc_slot = 0;
+    if (FUSED) {
+        const int64_t t = s_abs - a.run->trace_base;
+        const bool infer = (t >= 0) & (t < a.run->n_infer);
+        const int tm = infer ? (int)t : 0;
+        acc_slot = tm % 3;
+        if (infer && tm > 0) {
+            ctl = a.ictl[((tm - 1) & 1) * a.n_gc + it.gc];
+            const int64_t* A = a.gacc + ((int64_t)((tm - 1) % 3) * a.n_gc + it.gc) * kAccPerGc;
+            int64_t eh = 0, el = 0, na = 0;
+#pragma unroll
+            for (int k = 0; k < kAccCopies; ++k) {
+                eh += A[k * kAccWords];
+                el += A[k * kAccWords + 1];
+                na += A[k * kAccWords + 2];
+            }
+            const bool lead = wid == g.item_begin;
+            double* tr = (lead && lane == 0) ? a.trace + ((int64_t)it.gc * a.run->trace_cap + (tm - 1)) * 4 : nullptr;
+            control_step(ctl, -a.J * fix2_value(eh, el) / (double)g.n_bonds, na, g.n_pred,
+                         s_abs - 1 >= a.run->s_half, a.J, a.acc_target, a.T_min, a.T_max, 0.0,
+                         false, tr);
+            if (lead) {
+                if (lane == 0) a.ictl[(tm & 1) * a.n_gc + it.gc] = ctl;
+                if (lane < kAccPerGc) a.gacc[((int64_t)((tm + 1) % 3) * a.n_gc + it.gc) * kAccPerGc + lane] = 0;
+            }
+        } else {
+            ctl = infer ? a.ictl[it.gc] : a.ctl[it.gc];
+        }
+    } else {
+        ctl = a.ctl[it.gc];
+    }
 
     const F q = (F)a.q;
     const F J = (F)a.J;
@@ -562,7 +648,15 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
             else { e_hi += __shfl_xor(e_hi, off, kWave); e_lo += __shfl_xor(e_lo, off, kWave); }
         }
     }
-    if (lane == 0) {
+    if (FUSED) {
+        if (lane == 0) {
+            unsigned long long* A = (unsigned long long*)(a.gacc + ((int64_t)acc_slot * a.n_gc + it.gc) * kAccPerGc +
+                                                          (blockIdx.x & (kAccCopies - 1)) * kAccWords);
+            atomicAdd(A, (unsigned long long)e_hi);
+            atomicAdd(A + 1, (unsigned long long)e_lo);
+            atomicAdd(A + 2, (unsigned long long)(int64_t)n_acc);
+        }
+    } else if (lane == 0) {
         a.a_part[wid] = n_acc;
         if (FLAGS & F_ENERGY) {
             a.e_part[2 * wid] = ESINGLE ? (int64_t)__float_as_uint(e_flt) : e_hi;
