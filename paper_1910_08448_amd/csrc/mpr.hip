@@ -210,6 +210,10 @@ __global__ void k_infer_begin(GcCtl* ctl, GcCtl* ictl, int64_t* gacc, int n_gc, 
         run->s_half = s_half; run->trace_base = trace_base; run->trace_cap = trace_cap;
         run->n_infer = n_infer;
     }
+    if (i < 3 * n_gc * kAccCopies) {                // thread i clears copy i of all slots
+        int64_t* z = gacc + (int64_t)i * kAccStride;
+        z[0] = 0; z[1] = 0; z[2] = 0;
+    }
     if (i >= n_gc) return;
     GcCtl& c = ctl[i];
     const double T0 = fmin(fmax(4.0 * (c.e_smp + J), T_min), T_max);
@@ -218,8 +222,6 @@ __global__ void k_infer_begin(GcCtl* ctl, GcCtl* ictl, int64_t* gacc, int n_gc, 
     c.T_sum = 0.0;
     c.T_cnt = 0;
     ictl[i] = c;                                   // state of inference sweep 0
-    for (int slot = 0; slot < 3; ++slot)
-        for (int k = 0; k < kAccPerGc; ++k) gacc[((int64_t)slot * n_gc + i) * kAccPerGc + k] = 0;
 }
 
 // after n inference sweeps: with in-sweep control (double-precision energy) apply the control
@@ -237,9 +239,9 @@ __global__ void k_infer_end(const GcDesc* gcs, GcCtl* ctl, const GcCtl* ictl, co
         const int64_t* A = gacc + ((int64_t)(t % 3) * n_gc + i) * kAccPerGc;
         int64_t eh = 0, el = 0, na = 0;
         for (int k = 0; k < kAccCopies; ++k) {
-            eh += A[k * kAccWords];
-            el += A[k * kAccWords + 1];
-            na += A[k * kAccWords + 2];
+            eh += A[k * kAccStride];
+            el += A[k * kAccStride + 1];
+            na += A[k * kAccStride + 2];
         }
         const GcDesc g = gcs[i];
         control_step(c, -J * fix2_value(eh, el) / (double)g.n_bonds, na, g.n_pred,
@@ -588,7 +590,8 @@ static void build_items(mpr_ctx* c, int rows)
         d.item_begin = (int32_t)c->items.size();
         for (int y0 = 0; y0 < d.H; y0 += rows)
             for (int p0 = 0; p0 < d.np; p0 += kOutPairs)
-                c->items.push_back(Item{(int32_t)i, p0, y0, std::min(d.H, y0 + rows)});
+                c->items.push_back(Item{(int32_t)i, p0, y0, std::min(d.H, y0 + rows), d.plane_off,
+                                        d.H, d.W, d.np, d.pitch});
         d.item_end = (int32_t)c->items.size();
         max_items = std::max(max_items, d.item_end - d.item_begin);
     }
@@ -612,8 +615,10 @@ static int setup_shapes(mpr_ctx* c, int G, const int64_t* H, const int64_t* W)
             return fail(c, MPR_EINVAL, "grid %d: periodic boundary needs W divisible by 4", g);
         const int64_t np = ((W[g] + 1) / 2 + 1) / 2;
         const int64_t pitch = ((2 * np + 63) / 64) * 64;
-        if (2 * H[g] * pitch >= ((int64_t)1 << 31))
-            return fail(c, MPR_EINVAL, "grid %d: more than 2^30 sites per colour plane", g);
+        // the sweep addresses a (grid, chain)'s two planes of FP64 accumulators through one
+        // buffer resource of at most kBufMaxBytes
+        if (2 * H[g] * pitch * (int64_t)sizeof(double) > (int64_t)kBufMaxBytes)
+            return fail(c, MPR_EINVAL, "grid %d: too large (2 H pitch 8 bytes > %u)", g, kBufMaxBytes);
     }
     c->G = G;
     c->C = c->cfg.n_chains;
@@ -1013,7 +1018,7 @@ int mpr_infer_temperature(mpr_ctx* c, int32_t n_equil, double* T_host)
         for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);   // captured trace pointer
         c->graphs.clear();
     }
-    hipLaunchKernelGGL(k_infer_begin, dim3((n_gc + 255) / 256), dim3(256), 0, c->stream, c->d_ctl,
+    hipLaunchKernelGGL(k_infer_begin, dim3((3 * n_gc * kAccCopies + 255) / 256), dim3(256), 0, c->stream, c->d_ctl,
                        c->d_ictl, c->d_gacc, n_gc, c->cfg.J, c->cfg.T_min, c->cfg.T_max, c->d_run,
                        (int64_t)(c->next_sweep + n_equil / 2), (int64_t)c->next_sweep,
                        (int64_t)c->trace_cap, (int64_t)n_equil);

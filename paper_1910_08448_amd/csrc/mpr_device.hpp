@@ -35,6 +35,10 @@ struct GcDesc {            // one (grid, chain)
 
 struct Item {              // one wave's work: 60 output pairs x rows [y0, y1)
     int32_t gc, pair0, y0, y1;
+    // the (grid, chain)'s plane geometry, repeated here so a wave can address its rows after a
+    // single table read
+    int64_t plane_off;
+    int32_t H, W, np, pitch;
 };
 
 struct GcCtl {             // per (grid, chain) control state, device resident
@@ -54,19 +58,29 @@ struct RunCtl {            // per context, device resident
 
 // Inference sweeps in double-precision energy carry their own temperature control: sweep t of
 // an inference adds its exact integer sums (energy words, accepted moves) into slot t % 3 of the
-// per-(grid, chain) accumulators (kAccCopies copies, one per XCD-interleaved block class, to
-// spread the atomics), and every wave of sweep t > 0 first applies the control step of sweep
-// t - 1 from slot (t - 1) % 3 and the control state in slot (t - 1) & 1.  The first item of
-// each (grid, chain) stores the new state in slot t & 1, the trace entry of sweep t - 1, and
-// clears slot (t + 1) % 3 for the next sweep.  Kernel boundaries order all of it.
-constexpr int kAccCopies = 8;
-constexpr int kAccWords = 4;       // energy high word, energy low word, accepted moves, unused
-constexpr int kAccPerGc = kAccCopies * kAccWords;
+// per-(grid, chain) accumulators, and every wave of sweep t > 0 first applies the control step
+// of sweep t - 1 from slot (t - 1) % 3 and the control state in slot (t - 1) & 1.  The first
+// item of each (grid, chain) stores the new state in slot t & 1, the trace entry of sweep t - 1,
+// and clears slot (t + 1) % 3 for the next sweep.  Kernel boundaries order all of it.  Atomics
+// on one cache line serialise, so a slot holds kAccCopies copies a line apart (a block adds its
+// LDS-reduced sums to copy blockIdx % kAccCopies) and readers sum the copies (exact integers:
+// the order does not matter).
+constexpr int kAccCopies = 16;
+constexpr int kAccStride = 32;     // int64 words between copies (256 bytes)
+constexpr int kAccPerGc = kAccCopies * kAccStride;   // words 0, 1, 2 of a copy: energy high,
+                                                     // energy low, accepted moves
 
 enum { F_ENERGY = 1, F_ACC = 2, F_DEC = 4 };
 enum { DEC_OR = 1, DEC_ACCEPT = 2, DEC_OUTSIDE = 4 };
 
 constexpr int kWave = 64;
+#ifndef MPR_PREFETCH_ROWS
+#define MPR_PREFETCH_ROWS 1
+#endif
+constexpr int kPrefetchRows = MPR_PREFETCH_ROWS;   // rows of both colours loaded ahead of use
+#ifndef MPR_SKEW
+#define MPR_SKEW 1
+#endif
 constexpr int kOutPairs = 60;      // output pairs per wave (2 halo lanes on each side)
 constexpr int kWavesPerBlock = 4;
 
@@ -274,6 +288,70 @@ template <> struct Store<Fix15> {
     template <class F> static __device__ __forceinline__ F round(F u) { return value<F>(encode<F>(u)); }
 };
 
+// ------------------------------------------------------------------ buffer addressing
+// Plane accesses go through buffer resources: a byte offset at or past the resource's size reads
+// zeros and drops writes, so lanes and rows outside the grid or the output range need no branch
+// and every access issues, which lets the compiler wait for a load without also waiting for the
+// stores issued after it.  A resource covers at most kBufMaxBytes (checked on the host).
+using Rsrc = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+constexpr uint32_t kBufMaxBytes = 0xFFFFFF00u;
+constexpr uint32_t kBufOOB = 0xFFFFFF00u;          // offset that no resource covers
+
+__device__ __forceinline__ Rsrc make_rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <class St>
+__device__ __forceinline__ typename St::pair buf_load_pair(Rsrc r, uint32_t off)
+{
+    using raw = typename St::raw;
+    if constexpr (sizeof(raw) == 8) {
+        const u32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+        return {((uint64_t)v.y << 32) | v.x, ((uint64_t)v.w << 32) | v.z};
+    } else if constexpr (sizeof(raw) == 4) {
+        const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+        return {v.x, v.y};
+    } else {
+        const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+        return {(raw)(v & 0xffffu), (raw)(v >> 16)};
+    }
+}
+
+template <class St>
+__device__ __forceinline__ void buf_store_pair(Rsrc r, uint32_t off, typename St::pair p)
+{
+    using raw = typename St::raw;
+    if constexpr (sizeof(raw) == 8) {
+        u32x4_t v;
+        v.x = (uint32_t)p.a; v.y = (uint32_t)(p.a >> 32); v.z = (uint32_t)p.b; v.w = (uint32_t)(p.b >> 32);
+        __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)off, 0, 0);
+    } else if constexpr (sizeof(raw) == 4) {
+        u32x2_t v;
+        v.x = p.a; v.y = p.b;
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b32((uint32_t)p.a | ((uint32_t)p.b << 16), r, (int)off, 0, 0);
+    }
+}
+
+__device__ __forceinline__ double2 buf_load_f64x2(Rsrc r, uint32_t off)
+{
+    const u32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+    return make_double2(__longlong_as_double((long long)(((uint64_t)v.y << 32) | v.x)),
+                        __longlong_as_double((long long)(((uint64_t)v.w << 32) | v.z)));
+}
+
+__device__ __forceinline__ void buf_store_f64x2(Rsrc r, uint32_t off, double2 d)
+{
+    const uint64_t a = (uint64_t)__double_as_longlong(d.x), b = (uint64_t)__double_as_longlong(d.y);
+    u32x4_t v;
+    v.x = (uint32_t)a; v.y = (uint32_t)(a >> 32); v.z = (uint32_t)b; v.w = (uint32_t)(b >> 32);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)off, 0, 0);
+}
+
 // ------------------------------------------------------------------ per-site hybrid update
 // Input: current angle u (storage-rounded), local field (C, S) = sum_j (cos, sin)(2 pi q u_j),
 // uniforms.  Output: new angle (storage-rounded), its (cos, sin)(2 pi q u), decision bits.
@@ -434,11 +512,15 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
             ctl = a.ictl[((tm - 1) & 1) * a.n_gc + it.gc];
             const int64_t* A = a.gacc + ((int64_t)((tm - 1) % 3) * a.n_gc + it.gc) * kAccPerGc;
             int64_t eh = 0, el = 0, na = 0;
-#pragma unroll
-            for (int k = 0; k < kAccCopies; ++k) {
-                eh += A[k * kAccWords];
-                el += A[k * kAccWords + 1];
-                na += A[k * kAccWords + 2];
+            if (lane < kAccCopies) {
+                eh = A[lane * kAccStride];
+                el = A[lane * kAccStride + 1];
+                na = A[lane * kAccStride + 2];
+            }
+            for (int off = kWave / 2; off > 0; off >>= 1) {
+                eh += __shfl_xor(eh, off, kWave);
+                el += __shfl_xor(el, off, kWave);
+                na += __shfl_xor(na, off, kWave);
             }
             const bool lead = wid == g.item_begin;
             double* tr = (lead && lane == 0) ? a.trace + ((int64_t)it.gc * a.run->trace_cap + (tm - 1)) * 4 : nullptr;
@@ -447,7 +529,10 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
                          false, tr);
             if (lead) {
                 if (lane == 0) a.ictl[(tm & 1) * a.n_gc + it.gc] = ctl;
-                if (lane < kAccPerGc) a.gacc[((int64_t)((tm + 1) % 3) * a.n_gc + it.gc) * kAccPerGc + lane] = 0;
+                if (lane < kAccCopies) {
+                    int64_t* z = a.gacc + ((int64_t)((tm + 1) % 3) * a.n_gc + it.gc) * kAccPerGc + lane * kAccStride;
+                    z[0] = 0; z[1] = 0; z[2] = 0;
+                }
             }
         } else {
             ctl = infer ? a.ictl[it.gc] : a.ctl[it.gc];
@@ -463,36 +548,36 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
     // Boltzmann factor exp(-dE/T): float path 2^(dE * (-log2 e / T)), double path exp(dE * (-1/T))
     const F kexp = (sizeof(F) == 4) ? (F)(-1.4426950408889634 / ctl.T) : (F)(-1.0 / ctl.T);
 
-    const int H = g.H, np = g.np, pitch = g.pitch;
+    const int H = it.H, np = it.np, pitch = it.pitch;
     const int j = it.pair0 - 2 + lane;
     const bool in_range = (j >= 0) & (j < np);
     const int jj = PER ? ((j % np) + np) % np : j;        // periodic: W % 4 == 0, so wc is even
     const bool lane_ok = PER | in_range;
     const bool out_lane = (lane >= 2) & (lane < kWave - 2) & in_range;
     // site (y, c, m) of this lane has x = 4 jj + 2 m + ((y + c) & 1); it exists iff x < W
-    const int wl = g.W - 4 * jj;
+    const int wl = it.W - 4 * jj;
     const int col = 2 * jj;                              // plane column of member 0
-    const int plane_sz = H * pitch;                      // < 2^30 (checked on the host)
+    const int plane_sz = H * pitch;                      // 16 plane_sz <= kBufMaxBytes (host check)
 
-    // offsets count stored elements (the tag type of a fixed-point storage has no size of its own)
+    // this (grid, chain)'s two planes in the source and destination buffers, and its accumulators
+    // (offsets count stored elements: the tag type of a fixed-point storage has no size of its own)
     using Raw = typename St::raw;
-    const Raw* __restrict__ src = (const Raw*)a.src + g.plane_off;
-    Raw* __restrict__ dst = (Raw*)a.dst + g.plane_off;
+    constexpr uint32_t kRaw = (uint32_t)sizeof(Raw);
+    const uint32_t gc_elems = 2u * (uint32_t)plane_sz;
+    const Rsrc rs = make_rsrc((const Raw*)a.src + it.plane_off, gc_elems * kRaw);
+    const Rsrc rd = make_rsrc((Raw*)a.dst + it.plane_off, gc_elems * kRaw);
 
     auto row_ok = [&](int y) -> bool { return PER | ((y >= 0) & (y < H)); };
     auto wrap = [&](int y) -> int { return PER ? (y < 0 ? y + H : (y >= H ? y - H : y)) : y; };
-    // existence of member m at row parity p (= (y + c) & 1), rows aside
-    const bool ex_p0m0 = lane_ok & (0 < wl), ex_p0m1 = lane_ok & (2 < wl);
-    const bool ex_p1m0 = lane_ok & (1 < wl), ex_p1m1 = lane_ok & (3 < wl);
-    auto exists = [&](int y, int c, int m) -> bool {
-        const bool par = ((y + c) & 1) != 0;
-        const bool e = m ? (par ? ex_p1m1 : ex_p0m1) : (par ? ex_p1m0 : ex_p0m0);
-        return e & row_ok(y);
+    // existence of member m at row parity p (= (y + c) & 1), rows aside: bit 2 m + p of ex_bits
+    // (a value, not four addressable flags, so selecting one never goes through memory)
+    const int ex_bits = lane_ok ? ((0 < wl) ? 1 : 0) | ((1 < wl) ? 2 : 0) | ((2 < wl) ? 4 : 0) | ((3 < wl) ? 8 : 0) : 0;
+    auto exists = [=](int y, int c, int m) -> bool {
+        return (((ex_bits >> (2 * m + ((y + c) & 1))) & 1) != 0) & row_ok(y);
     };
     auto load_pair = [&](int c, int y) -> Pair {
-        Pair p = {0, 0};
-        if (lane_ok & row_ok(y)) p = St::load(src, c * plane_sz + wrap(y) * pitch + col);
-        return p;
+        const uint32_t off = (lane_ok & row_ok(y)) ? (uint32_t)(c * plane_sz + wrap(y) * pitch + col) * kRaw : kBufOOB;
+        return buf_load_pair<St>(rs, off);
     };
     auto cs_of = [&](Pair p, int y, int c) -> RowCS<F> {
         RowCS<F> r;
@@ -557,6 +642,131 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
 
     const int ya = it.y0, yb = it.y1;
     const RowCS<F> zero = {(F)0, (F)0, (F)0, (F)0};
+    // loads run kPrefetchRows rows ahead of their use; rows past y1 + 1 are never used and not
+    // loaded
+    auto load_ahead = [&](int c, int y) -> Pair { return (y <= yb + 1) ? load_pair(c, y) : Pair{0, 0}; };
+
+    // stores row y of both colours (new colour-0 pair n0 with its decisions, new colour-1 pair
+    // n1) and accumulates the per-row outputs
+    auto finish_row = [&](int y, const Pair& n0, int d0a, int d0b, const Pair& n1, int d1a,
+                          int d1b, F e) {
+        // non-output lanes address past the resources: their stores are dropped
+        const uint32_t r0 = (uint32_t)(y * pitch + col);
+        const uint32_t r1 = (uint32_t)plane_sz + r0;
+        buf_store_pair<St>(rd, out_lane ? r0 * kRaw : kBufOOB, n0);
+        buf_store_pair<St>(rd, out_lane ? r1 * kRaw : kBufOOB, n1);
+        n_acc += out_lane ? ((d0a >> 1) & 1) + ((d0b >> 1) & 1) + ((d1a >> 1) & 1) + ((d1b >> 1) & 1) : 0;
+        if (FLAGS & F_ENERGY) {
+            const F eo = out_lane ? e : (F)0;
+            if (ESINGLE) e_flt += (float)eo;
+            else { const Fix2 f = fixed64x2((double)eo); e_hi += f.hi; e_lo += f.lo; }
+        }
+        if (FLAGS & F_ACC) {
+            const Rsrc ra = make_rsrc(a.acc + it.plane_off, gc_elems * 8u);
+            const uint32_t o0 = out_lane ? r0 * 8u : kBufOOB, o1 = out_lane ? r1 * 8u : kBufOOB;
+            const bool f0a = exists(y, 0, 0) & !St::sample(n0.a);
+            const bool f0b = exists(y, 0, 1) & !St::sample(n0.b);
+            const bool f1a = exists(y, 1, 0) & !St::sample(n1.a);
+            const bool f1b = exists(y, 1, 1) & !St::sample(n1.b);
+            double2 p0 = buf_load_f64x2(ra, o0);
+            double2 p1 = buf_load_f64x2(ra, o1);
+            if (f0a) p0.x += St::template value<double>(n0.a);
+            if (f0b) p0.y += St::template value<double>(n0.b);
+            if (f1a) p1.x += St::template value<double>(n1.a);
+            if (f1b) p1.y += St::template value<double>(n1.b);
+            buf_store_f64x2(ra, o0, p0);
+            buf_store_f64x2(ra, o1, p1);
+        }
+        if ((FLAGS & F_DEC) && out_lane) {
+            uint8_t* d = a.dec + g.site_off + (int64_t)y * g.W;
+            const int xb = 4 * jj;
+            const int o0 = y & 1, o1 = (y + 1) & 1;
+            if (exists(y, 0, 0)) d[xb + o0] = (uint8_t)d0a;
+            if (exists(y, 0, 1)) d[xb + 2 + o0] = (uint8_t)d0b;
+            if (exists(y, 1, 0)) d[xb + o1] = (uint8_t)d1a;
+            if (exists(y, 1, 1)) d[xb + 2 + o1] = (uint8_t)d1b;
+        }
+    };
+
+#if MPR_SKEW
+    // Skewed pipeline: iteration k updates colour 0 at row k and colour 1 at row k - 2.  The two
+    // updates share no data (colour 1 at row k - 2 needs the new colour 0 of rows k - 3 ... k - 1
+    // only), so in the steady state they form one branch-free block the scheduler interleaves:
+    // twice the independent work per wave of a one-row lag.
+    // window: colour-1 old raw rows k-2 ... k+1 and (cos, sin) rows k-1 ... k+1; colour-0 new
+    // (cos, sin) rows k-3 ... k, raw rows and decisions k-2 ... k
+    Pair v0_cur, v0_next, r1_m2, r1_m1 = Pair{0, 0}, r1_0, r1_p1;
+    RowCS<F> w1_m1, w1_0, w1_p1;
+    RowCS<F> w0_m3, w0_m2 = zero, w0_m1 = zero, w0_0 = zero;
+    Pair n0_m2, n0_m1 = Pair{0, 0}, n0_0 = Pair{0, 0};
+    int d0_m2a, d0_m2b, d0_m1a = 0, d0_m1b = 0, d0_0a = 0, d0_0b = 0;
+
+    r1_0 = load_pair(1, ya - 2);
+    w1_0 = cs_of(r1_0, ya - 2, 1);
+    r1_p1 = load_pair(1, ya - 1);
+    w1_p1 = cs_of(r1_p1, ya - 1, 1);
+    v0_next = load_pair(0, ya - 1);
+    Pair pf1[kPrefetchRows], pf0[kPrefetchRows];
+#pragma unroll
+    for (int d = 0; d < kPrefetchRows; ++d) {
+        pf1[d] = load_ahead(1, ya + d);
+        pf0[d] = load_ahead(0, ya + d);
+    }
+
+    auto step = [&](int k, bool c0_rows_checked, bool do_c0, bool do_c1) __attribute__((always_inline)) {
+        w1_m1 = w1_0; w1_0 = w1_p1;
+        r1_m2 = r1_m1; r1_m1 = r1_0; r1_0 = r1_p1;
+        w0_m3 = w0_m2; w0_m2 = w0_m1; w0_m1 = w0_0;
+        n0_m2 = n0_m1; n0_m1 = n0_0;
+        d0_m2a = d0_m1a; d0_m2b = d0_m1b; d0_m1a = d0_0a; d0_m1b = d0_0b;
+        v0_cur = v0_next;
+        r1_p1 = pf1[0];
+        v0_next = pf0[0];
+#pragma unroll
+        for (int d = 0; d + 1 < kPrefetchRows; ++d) {
+            pf1[d] = pf1[d + 1];
+            pf0[d] = pf0[d + 1];
+        }
+        pf1[kPrefetchRows - 1] = load_ahead(1, k + 1 + kPrefetchRows);
+        pf0[kPrefetchRows - 1] = load_ahead(0, k + 1 + kPrefetchRows);
+        if (do_c0) w1_p1 = cs_of(r1_p1, k + 1, 1);
+        if (do_c0 && (!c0_rows_checked || row_ok(k))) {
+            F e_unused;
+            update_row(v0_cur, w1_m1, w1_0, w1_p1, k, 0, n0_0, w0_0, d0_0a, d0_0b, e_unused);
+        } else {
+            n0_0 = v0_cur;
+            w0_0 = zero;
+            d0_0a = d0_0b = 0;
+        }
+        if (do_c1) {
+            const int y = k - 2;
+            Pair n1;
+            RowCS<F> cs1;
+            int d1a, d1b;
+            F e;
+            update_row(r1_m2, w0_m3, w0_m2, w0_m1, y, 1, n1, cs1, d1a, d1b, e);
+            finish_row(y, n0_m2, d0_m2a, d0_m2b, n1, d1a, d1b, e);
+        } else {
+            // the same memory operations, all out of range: every path into the steady loop
+            // then has the same count of stores behind the loads, and the compiler can wait for
+            // the loads alone
+            buf_store_pair<St>(rd, kBufOOB, Pair{0, 0});
+            buf_store_pair<St>(rd, kBufOOB, Pair{0, 0});
+            if (FLAGS & F_ACC) {
+                const Rsrc ra = make_rsrc(a.acc + it.plane_off, gc_elems * 8u);
+                const double2 p0 = buf_load_f64x2(ra, kBufOOB), p1 = buf_load_f64x2(ra, kBufOOB);
+                buf_store_f64x2(ra, kBufOOB, p0);
+                buf_store_f64x2(ra, kBufOOB, p1);
+            }
+        }
+    };
+    // fill: colour 0 only (rows ya-1 ... ya+1); steady state: both colours, rows in the grid;
+    // drain: colour 0 of row yb (if in the grid) and colour 1 of the last two rows
+    int k = ya - 1;
+    for (; k <= ya + 1 && k <= yb; ++k) step(k, true, true, false);
+    for (; k <= yb - 1; ++k) step(k, false, true, true);
+    for (; k <= yb + 1; ++k) step(k, true, k <= yb, k - 2 >= ya);
+#else
     // window: colour-1 old rows k-1, k, k+1; colour-0 new rows k-2, k-1, k
     Pair v0_cur, v0_next, v1_m1, v1_0, v1_p1;
     RowCS<F> w1_m1, w1_0, w1_p1;
@@ -572,8 +782,12 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
     w0_m1 = zero;
     w0_0 = zero;
     n0_0 = Pair{0, 0};
-    // loads run one row ahead of their use, so their latency overlaps a row of arithmetic
-    Pair pf1 = load_pair(1, ya), pf0 = load_pair(0, ya);
+    Pair pf1[kPrefetchRows], pf0[kPrefetchRows];
+#pragma unroll
+    for (int d = 0; d < kPrefetchRows; ++d) {
+        pf1[d] = load_ahead(1, ya + d);
+        pf0[d] = load_ahead(0, ya + d);
+    }
 
     // iteration k: load row k+1, colour-0 update of row k, colour-1 update and store of row k-1
     for (int k = ya - 1; k <= yb; ++k) {
@@ -583,10 +797,15 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
         n0_m1 = n0_0;
         d0_m1a = d0_0a; d0_m1b = d0_0b;
         v0_cur = v0_next;
-        v1_p1 = pf1;
-        v0_next = pf0;
-        pf1 = load_pair(1, k + 2);
-        pf0 = load_pair(0, k + 2);
+        v1_p1 = pf1[0];
+        v0_next = pf0[0];
+#pragma unroll
+        for (int d = 0; d + 1 < kPrefetchRows; ++d) {
+            pf1[d] = pf1[d + 1];
+            pf0[d] = pf0[d + 1];
+        }
+        pf1[kPrefetchRows - 1] = load_ahead(1, k + 1 + kPrefetchRows);
+        pf0[kPrefetchRows - 1] = load_ahead(0, k + 1 + kPrefetchRows);
         w1_p1 = cs_of(v1_p1, k + 1, 1);
         if (row_ok(k)) {
             F e_unused;
@@ -603,42 +822,11 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
             int d1a, d1b;
             F e;
             update_row(v1_m1, w0_m2, w0_m1, w0_0, y, 1, n1, cs1, d1a, d1b, e);
-            if (out_lane) {
-                const int r0 = y * pitch + col;
-                St::store(dst, r0, n0_m1);
-                St::store(dst, plane_sz + r0, n1);
-                n_acc += ((d0_m1a >> 1) & 1) + ((d0_m1b >> 1) & 1) + ((d1a >> 1) & 1) + ((d1b >> 1) & 1);
-                if (FLAGS & F_ENERGY) {
-                    if (ESINGLE) e_flt += (float)e;
-                    else { const Fix2 f = fixed64x2((double)e); e_hi += f.hi; e_lo += f.lo; }
-                }
-                if (FLAGS & F_ACC) {
-                    const bool f0a = exists(y, 0, 0) & !St::sample(n0_m1.a);
-                    const bool f0b = exists(y, 0, 1) & !St::sample(n0_m1.b);
-                    const bool f1a = exists(y, 1, 0) & !St::sample(n1.a);
-                    const bool f1b = exists(y, 1, 1) & !St::sample(n1.b);
-                    double* acc = a.acc + g.plane_off;
-                    double2 p0 = *((double2*)(acc + r0));
-                    double2 p1 = *((double2*)(acc + plane_sz + r0));
-                    if (f0a) p0.x += St::template value<double>(n0_m1.a);
-                    if (f0b) p0.y += St::template value<double>(n0_m1.b);
-                    if (f1a) p1.x += St::template value<double>(n1.a);
-                    if (f1b) p1.y += St::template value<double>(n1.b);
-                    *((double2*)(acc + r0)) = p0;
-                    *((double2*)(acc + plane_sz + r0)) = p1;
-                }
-                if (FLAGS & F_DEC) {
-                    uint8_t* d = a.dec + g.site_off + (int64_t)y * g.W;
-                    const int xb = 4 * jj;
-                    const int o0 = y & 1, o1 = (y + 1) & 1;
-                    if (exists(y, 0, 0)) d[xb + o0] = (uint8_t)d0_m1a;
-                    if (exists(y, 0, 1)) d[xb + 2 + o0] = (uint8_t)d0_m1b;
-                    if (exists(y, 1, 0)) d[xb + o1] = (uint8_t)d1a;
-                    if (exists(y, 1, 1)) d[xb + 2 + o1] = (uint8_t)d1b;
-                }
-            }
+            finish_row(y, n0_m1, d0_m1a, d0_m1b, n1, d1a, d1b, e);
         }
     }
+
+#endif
 
     // wave reductions -> per-item partials (exact integers, or a fixed-order float tree)
     for (int off = kWave / 2; off > 0; off >>= 1) {
@@ -649,9 +837,27 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
         }
     }
     if (FUSED) {
-        if (lane == 0) {
-            unsigned long long* A = (unsigned long long*)(a.gacc + ((int64_t)acc_slot * a.n_gc + it.gc) * kAccPerGc +
-                                                          (blockIdx.x & (kAccCopies - 1)) * kAccWords);
+        unsigned long long* A = (unsigned long long*)(a.gacc + ((int64_t)acc_slot * a.n_gc + it.gc) * kAccPerGc);
+        // a full block of one (grid, chain) adds once (block-uniform test: every wave of the
+        // block takes the same branch, so all or none reach the barrier)
+        const int b0 = (int)blockIdx.x * kWavesPerBlock;
+        const bool whole = (b0 + kWavesPerBlock <= a.n_items) &&
+                           (a.items[b0].gc == a.items[b0 + kWavesPerBlock - 1].gc);
+        if (whole) {
+            __shared__ int64_t red[kWavesPerBlock][3];
+            const int w = (int)(threadIdx.x >> 6);
+            if (lane == 0) { red[w][0] = e_hi; red[w][1] = e_lo; red[w][2] = (int64_t)n_acc; }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int64_t s0 = 0, s1 = 0, s2 = 0;
+                for (int k = 0; k < kWavesPerBlock; ++k) { s0 += red[k][0]; s1 += red[k][1]; s2 += red[k][2]; }
+                A += (blockIdx.x & (kAccCopies - 1)) * kAccStride;
+                atomicAdd(A, (unsigned long long)s0);
+                atomicAdd(A + 1, (unsigned long long)s1);
+                atomicAdd(A + 2, (unsigned long long)s2);
+            }
+        } else if (lane == 0) {
+            A += (wid & (kAccCopies - 1)) * kAccStride;
             atomicAdd(A, (unsigned long long)e_hi);
             atomicAdd(A + 1, (unsigned long long)e_lo);
             atomicAdd(A + 2, (unsigned long long)(int64_t)n_acc);
