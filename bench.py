@@ -7,9 +7,13 @@ second over the whole step: one site update = one hybrid (over-relaxation + Metr
 of one prediction site in one sweep of one chain.
 
 Also printed in the same JSON line:
-  roofline      the sweep kernel's algorithmic HBM bytes per launch (other colour read, own
-                prediction sites read and written: (N + 2P) s per chain, s = bytes per angle)
-                over its average launch time, measured with HIP events on the library's stream
+  roofline      the sweep kernel against the vector-ALU roof it is bound by: the method's
+                arithmetic per site update (OPS_PER_UPDATE FP32-rate issue slots, see below)
+                times the site updates of one launch, over the kernel's average launch time
+                (HIP events on the library's stream); its algorithmic HBM bytes ((N + 2P) s per
+                chain, s = bytes per angle) against the 8 TB/s HBM roof are reported beside it,
+                and `traffic` is the HBM bytes per launch that rocprofv3 counted for the same
+                kernel source (null when the kernel changed since the counters were taken)
   cpu_baseline  the FP64 CPU oracle timed on a bounded sample of the same workload
   setups        the same measurements for the other precision setups / workloads
 """
@@ -27,6 +31,16 @@ sys.path.insert(0, ROOT)
 from paper_1910_08448_amd import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector issue slots per second: 157.3 TFLOP/s counts a fused multiply-add as 2 flops
+ALU_PEAK_TOPS = 157.3 / 2
+# The method's arithmetic per site update, in FP32-rate issue slots (a transcendental and a
+# 32 x 32 -> 64-bit multiply count 4, at a quarter of the rate): field sums 6, over-relaxation
+# (atan2 16, reflection and range test 5) 21, (cos, sin) of the current angle 9, half a
+# Philox4x32-10 call (10 rounds of two 4-slot multiplies and two xors) 50, Metropolis (two
+# uniforms, proposal and range test, its (cos, sin), the energy change, exp, accept and
+# select) 30, energy and acceptance sums 3.
+OPS_PER_UPDATE = 119
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 PREC = {"fp64": 0, "fp32": 1, "fp16": 2, "fix16": 3}
 BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "fix16": 2}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16": "f32", "fix16": "f32"}   # arithmetic type of the sweep
@@ -35,6 +49,31 @@ SWEEPS = {"grid64": (256, 100), "grid1024": (1000, 100), "grid4096": (1000, 100)
 CHAINS = {"batch256": 4}
 EXTENDED = [("grid4096", "fp16"), ("grid16384", "fp16"), ("grid16384", "fp32"),
             ("grid16384", "fp64"), ("batch256", "fp16"), ("batch256", "fp32")]
+
+
+def kernel_source_sha():
+    """Digest of the sources the sweep kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("mpr_device.hpp", "mpr.hip"):
+        with open(os.path.join(ROOT, "paper_1910_08448_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per launch of the inference sweep kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by its reading for a copy of known size),
+    or None when there is none for this workload or the kernel source changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get("entries", {}).get("%s/%s" % (workload, precision))
+    if e is None or t.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return int(e["bytes_per_launch"])
 
 
 def log(*a):
@@ -77,14 +116,17 @@ def oracle_reference(name, p_missing):
     return json.load(open(path)).get(key)
 
 
-def measure(inp, precision, steps, warmup, kernel_launches, torch, M):
+SWEEP_MODE = {"auto": 0, "fused": 1, "sparse": 2}
+
+
+def measure(inp, precision, steps, warmup, kernel_launches, torch, M, sweep_mode="auto"):
     chains = CHAINS.get(inp.name, 1)
     n_equil, n_avg = SWEEPS[inp.name]
     P = sum(inp.n_pred) * chains
     updates_per_step = P * (n_equil + n_avg)
     stream = torch.cuda.Stream()
     ctx = M.Context(shapes=inp.shapes, stream=stream, precision=PREC[precision], n_chains=chains,
-                    seed=inp.mc_seed)
+                    seed=inp.mc_seed, sweep_mode=SWEEP_MODE[sweep_mode])
     zhat = torch.empty(sum(inp.n_sites), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
 
@@ -128,19 +170,27 @@ def measure(inp, precision, steps, warmup, kernel_launches, torch, M):
         ev1.record(stream)
     ev1.synchronize()
     kernel_ms = ev0.elapsed_time(ev1) / kernel_launches
+    path = "sparse" if ctx.sweep_mode() == M.SWEEP_SPARSE else "fused"
+    kernel_name = ("k_sparse<colour 0> + k_sparse<colour 1> (inference variant, one sweep)"
+                   if path == "sparse" else "k_sweep (inference variant)")
     s = BYTES[precision]
     alg_bytes = sum((n + 2 * p) * s for n, p in zip(inp.n_sites, inp.n_pred)) * chains
-    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_sweep (inference variant)", "kernel_ms": round(kernel_ms, 5),
-                "bytes_per_launch": alg_bytes,
-                "site_updates_per_launch": P}
+    gbs = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    ops = OPS_PER_UPDATE * P
+    tops = ops / (kernel_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(tops, 3), "peak": ALU_PEAK_TOPS,
+                "unit": "TOP/s", "frac": round(tops / ALU_PEAK_TOPS, 4),
+                "traffic": measured_traffic(inp.name, precision),
+                "kernel": kernel_name, "kernel_ms": round(kernel_ms, 5),
+                "ops_per_launch": ops, "ops_per_site_update": OPS_PER_UPDATE,
+                "site_updates_per_launch": P,
+                "hbm": {"achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": alg_bytes}}
     ctx.close()
     out = {"workload": inp.name, "precision": precision, "value": value,
            "unit": "site-updates/s", "ms_per_step": ms_per_step, "steps": steps,
            "grids": len(inp.shapes), "sites": sum(inp.n_sites), "prediction_sites": sum(inp.n_pred),
-           "chains": chains, "n_equil": n_equil, "n_avg": n_avg, "mae": mae, "rmse": rmse,
+           "chains": chains, "sweep_path": path, "n_equil": n_equil, "n_avg": n_avg, "mae": mae, "rmse": rmse,
            "T_hat": T_hat[:4], "roofline": roofline}
     ref = oracle_reference(inp.name, inp.p_missing)
     if ref is not None and chains == ref["chains"]:
@@ -183,6 +233,8 @@ def main():
     ap.add_argument("--workload", default="grid1024", choices=sorted(SWEEPS))
     ap.add_argument("--precision", default="fp32", choices=sorted(PREC))
     ap.add_argument("--p-missing", type=float, default=None)
+    ap.add_argument("--sweep-mode", default="auto", choices=sorted(SWEEP_MODE),
+                    help="sweep path: automatic choice, fused row blocks, or compacted site lists")
     ap.add_argument("--kernel-launches", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -212,7 +264,7 @@ def main():
         del a, b
     inputs = {args.workload: Inputs(args.workload, args.p_missing, torch)}
     prim = measure(inputs[args.workload], args.precision, args.steps, args.warmup,
-                   args.kernel_launches, torch, M)
+                   args.kernel_launches, torch, M, args.sweep_mode)
 
     setups = []
     if not args.no_setups:
@@ -227,7 +279,8 @@ def main():
                 torch.cuda.empty_cache()
                 inputs[wl] = Inputs(wl, None, torch)
             steps = max(1, min(args.steps, 3)) if wl != args.workload else args.steps
-            setups.append(measure(inputs[wl], prec, steps, 1, args.kernel_launches, torch, M))
+            setups.append(measure(inputs[wl], prec, steps, 1, args.kernel_launches, torch, M,
+                                  args.sweep_mode))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -243,7 +296,8 @@ def main():
         "config": {"workload": args.workload, "precision": args.precision,
                    "grids": prim["grids"], "sites": prim["sites"],
                    "prediction_sites": prim["prediction_sites"], "chains": prim["chains"],
-                   "n_equil": prim["n_equil"], "n_avg": prim["n_avg"]},
+                   "n_equil": prim["n_equil"], "n_avg": prim["n_avg"],
+                   "sweep_path": prim["sweep_path"]},
         "mae": prim["mae"], "rmse": prim["rmse"], "T_hat": prim["T_hat"],
         "roofline": prim["roofline"],
         "cpu_baseline": cpu,

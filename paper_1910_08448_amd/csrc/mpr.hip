@@ -3,6 +3,7 @@
 // control, averaging finalisation, checkpoint gather and scatter.
 #include "mpr.h"
 #include "mpr_device.hpp"
+#include "mpr_sparse.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -201,9 +202,9 @@ __global__ __launch_bounds__(256) void k_copy_z(const GridInfo* gi, const double
 }
 
 // ------------------------------------------------------------------ control kernels
-__global__ void k_infer_begin(GcCtl* ctl, GcCtl* ictl, int64_t* gacc, int n_gc, double J,
-                              double T_min, double T_max, RunCtl* run, int64_t s_half,
-                              int64_t trace_base, int64_t trace_cap, int64_t n_infer)
+__global__ void k_infer_begin(GcCtl* ctl, GcCtl* ictl, int64_t* gacc, const int64_t* econst,
+                              int n_gc, double J, double T_min, double T_max, RunCtl* run,
+                              int64_t s_half, int64_t trace_base, int64_t trace_cap, int64_t n_infer)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) {
@@ -212,7 +213,11 @@ __global__ void k_infer_begin(GcCtl* ctl, GcCtl* ictl, int64_t* gacc, int n_gc, 
     }
     if (i < 3 * n_gc * kAccCopies) {                // thread i clears copy i of all slots
         int64_t* z = gacc + (int64_t)i * kAccStride;
-        z[0] = 0; z[1] = 0; z[2] = 0;
+        const int gc = (i / kAccCopies) % n_gc;
+        const bool first = econst && (i % kAccCopies) == 0;   // copy 0 starts at the constant
+        z[0] = first ? econst[2 * gc] : 0;
+        z[1] = first ? econst[2 * gc + 1] : 0;
+        z[2] = 0;
     }
     if (i >= n_gc) return;
     GcCtl& c = ctl[i];
@@ -401,6 +406,165 @@ __global__ __launch_bounds__(256) void k_set_state(const GcDesc* gcs, void* st, 
     }
 }
 
+// ------------------------------------------------------------------ site lists (compacted path)
+// Prediction sites of plane c, row y of grid gr (its first chain's planes: all chains share
+// the mask): those with x = 2k + ((y + c) & 1) < W and no sample flag.
+template <class S>
+__device__ __forceinline__ bool listed_site(const typename Store<S>::raw* row, int k, int par, int W, int pitch)
+{
+    return (k < pitch) && (2 * k + par < W) && !Store<S>::sample(row[k < pitch ? k : 0]);
+}
+
+template <class T> __device__ __forceinline__ T block_sum256(T v, T* sh)
+{
+    v = wave_sum(v);
+    if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    T t = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return t;
+}
+
+// row counts: block (row y, grid gr * 2 + colour c), 256 threads
+template <class S>
+__global__ __launch_bounds__(256) void k_list_count(const GcDesc* gcs, int n_chains, const void* st,
+                                                    int32_t* row_cnt, const int64_t* row_off)
+{
+    using St = Store<S>;
+    __shared__ int sh[4];
+    const int gr = blockIdx.y >> 1, c = blockIdx.y & 1;
+    const GcDesc g = gcs[gr * n_chains];
+    const int y = blockIdx.x;
+    if (y >= g.H) return;                                    // uniform over the block
+    const typename St::raw* row = (const typename St::raw*)st + g.plane_off +
+                                  ((int64_t)c * g.H + y) * g.pitch;
+    int cnt = 0;
+    for (int k0 = 0; k0 < g.pitch; k0 += 256)
+        cnt += listed_site<S>(row, k0 + (int)threadIdx.x, (y + c) & 1, g.W, g.pitch) ? 1 : 0;
+    cnt = block_sum256(cnt, sh);
+    if (threadIdx.x == 0) row_cnt[row_off[gr] + (int64_t)c * g.H + y] = cnt;
+}
+
+// exclusive scan of the row counts of (grid, colour) = blockIdx.x into row starts (in place);
+// totals[blockIdx.x] receives the number of listed sites
+__global__ __launch_bounds__(256) void k_list_scan(const GcDesc* gcs, int n_chains, int32_t* row_cnt,
+                                                   const int64_t* row_off, int32_t* totals)
+{
+    __shared__ int sh[4];
+    const int gr = blockIdx.x >> 1, c = blockIdx.x & 1;
+    const GcDesc g = gcs[gr * n_chains];
+    int32_t* r = row_cnt + row_off[gr] + (int64_t)c * g.H;
+    int base = 0;
+    for (int y0 = 0; y0 < g.H; y0 += 256) {
+        const int y = y0 + (int)threadIdx.x;
+        const int v = y < g.H ? r[y] : 0;
+        // inclusive scan inside the wave, then across the four waves
+        int inc = v;
+        const int lane = threadIdx.x & (kWave - 1);
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int t = __shfl_up(inc, off, kWave);
+            if (lane >= off) inc += t;
+        }
+        if (lane == kWave - 1) sh[threadIdx.x >> 6] = inc;
+        __syncthreads();
+        int wbase = 0;
+        for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wbase += sh[w];
+        const int total = sh[0] + sh[1] + sh[2] + sh[3];
+        if (y < g.H) r[y] = base + wbase + inc - v;
+        base += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = base;
+}
+
+// fill: block (row y, grid * 2 + colour) writes its row's sites in column order at
+// list_base[grid * 2 + colour] + row start
+template <class S>
+__global__ __launch_bounds__(256) void k_list_fill(const GcDesc* gcs, int n_chains, const void* st,
+                                                   const int32_t* row_start, const int64_t* row_off,
+                                                   const int64_t* list_base, uint32_t* sites)
+{
+    using St = Store<S>;
+    __shared__ int sh[4];
+    const int gr = blockIdx.y >> 1, c = blockIdx.y & 1;
+    const GcDesc g = gcs[gr * n_chains];
+    const int y = blockIdx.x;
+    if (y >= g.H) return;                                    // uniform over the block
+    const typename St::raw* row = (const typename St::raw*)st + g.plane_off +
+                                  ((int64_t)c * g.H + y) * g.pitch;
+    int64_t pos = list_base[blockIdx.y] + row_start[row_off[gr] + (int64_t)c * g.H + y];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+    for (int k0 = 0; k0 < g.pitch; k0 += 256) {
+        const int k = k0 + (int)threadIdx.x;
+        const bool f = listed_site<S>(row, k, (y + c) & 1, g.W, g.pitch);
+        const unsigned long long m = __ballot(f);
+        const int before = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) sh[w] = __popcll(m);
+        __syncthreads();
+        int wbase = 0;
+        for (int i = 0; i < w; ++i) wbase += sh[i];
+        const int total = sh[0] + sh[1] + sh[2] + sh[3];
+        if (f) sites[pos + wbase + before] = ((uint32_t)y << 16) | (uint32_t)k;
+        pos += total;
+        __syncthreads();
+    }
+}
+
+// energy of the sample-sample bonds of (grid, chain) blockIdx.y from the stored values, as the
+// compacted path's colour kernels would sum it: per colour-1 sample site, its bonds to colour-0
+// samples, c cos + s sin in the compute precision, two-word fixed point
+template <class S, class F, bool PER>
+__global__ __launch_bounds__(256) void k_econst(const GcDesc* gcs, const void* st, double q,
+                                                int64_t* econst)
+{
+    using St = Store<S>;
+    using M = Math<F>;
+    __shared__ int64_t sh[4];
+    const GcDesc g = gcs[blockIdx.y];
+    const typename St::raw* p = (const typename St::raw*)st + g.plane_off;
+    const int64_t plane = (int64_t)g.H * g.pitch;
+    int64_t e_hi = 0, e_lo = 0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < plane;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(e / g.pitch), k = (int)(e - (int64_t)y * g.pitch);
+        const int x = 2 * k + ((y + 1) & 1);
+        if (x >= g.W) continue;
+        const typename St::raw v = p[plane + e];
+        if (!St::sample(v)) continue;
+        int xl = x - 1, xr = x + 1, yu = y - 1, yd = y + 1;
+        bool el = xl >= 0, er = xr < g.W, eu = yu >= 0, ed = yd < g.H;
+        if (PER) {
+            xl = el ? xl : xl + g.W; xr = er ? xr : xr - g.W;
+            yu = eu ? yu : yu + g.H; yd = ed ? yd : yd - g.H;
+            el = er = eu = ed = true;
+        }
+        F C = (F)0, S_ = (F)0;
+        F cs[4], sn[4];
+        const int ys[4] = {y, y, yu, yd}, xs[4] = {xl, xr, x, x};
+        const bool ex[4] = {el, er, eu, ed};
+        for (int n = 0; n < 4; ++n) {
+            cs[n] = (F)0; sn[n] = (F)0;
+            if (!ex[n]) continue;
+            const typename St::raw r = p[(int64_t)ys[n] * g.pitch + (xs[n] >> 1)];
+            if (!St::sample(r)) continue;
+            M::sincos_rev((F)q * St::template value<F>(r), sn[n], cs[n]);
+        }
+        C = (cs[0] + cs[1]) + (cs[2] + cs[3]);
+        S_ = (sn[0] + sn[1]) + (sn[2] + sn[3]);
+        F s0, c0;
+        M::sincos_rev((F)q * St::template value<F>(v), s0, c0);
+        const Fix2 f = fixed64x2((double)M::fma(c0, C, s0 * S_));
+        e_hi += f.hi;
+        e_lo += f.lo;
+    }
+    e_hi = block_sum256(e_hi, sh);
+    e_lo = block_sum256(e_lo, sh);
+    if (threadIdx.x == 0) {
+        atomicAdd((unsigned long long*)&econst[2 * blockIdx.y], (unsigned long long)e_hi);
+        atomicAdd((unsigned long long*)&econst[2 * blockIdx.y + 1], (unsigned long long)e_lo);
+    }
+}
+
 // ------------------------------------------------------------------ sweep kernel table
 using SweepFn = void (*)(SweepArgs);
 
@@ -417,6 +581,24 @@ template <class S, class F, bool PER> SweepFn pick_sweep_b(int flags, bool esing
 template <class S, class F> SweepFn pick_sweep(int flags, bool esingle, bool per)
 {
     return per ? pick_sweep_b<S, F, true>(flags, esingle) : pick_sweep_b<S, F, false>(flags, esingle);
+}
+
+using SparseFn = void (*)(SparseArgs);
+
+template <class S, class F, bool PER, int C> SparseFn pick_sparse_c(int flags)
+{
+    switch (flags) {
+    case 0: return k_sparse<S, F, 0, PER, C>;
+    case F_ENERGY: return k_sparse<S, F, F_ENERGY, PER, C>;
+    case F_ACC: return k_sparse<S, F, F_ACC, PER, C>;
+    default: return k_sparse<S, F, F_DEC, PER, C>;
+    }
+}
+
+template <class S, class F> SparseFn pick_sparse(int flags, bool per, int colour)
+{
+    if (per) return colour ? pick_sparse_c<S, F, true, 1>(flags) : pick_sparse_c<S, F, true, 0>(flags);
+    return colour ? pick_sparse_c<S, F, false, 1>(flags) : pick_sparse_c<S, F, false, 0>(flags);
 }
 
 }  // namespace
@@ -468,6 +650,18 @@ struct mpr_ctx {
     int rows = 16;                                           // rows per work item
     int ctl_threads = 64;                                    // block size of the control kernel
     int64_t item_cap = 0;                                    // items at the smallest row block
+    // compacted path (sweep_mode SPARSE): per colour, the prediction-site lists of every grid
+    // (shared by its chains) and the waves over them
+    bool sparse = false;
+    uint32_t* d_sites = nullptr;
+    int64_t sites_cap = 0;
+    int2* d_waves[2] = {nullptr, nullptr};
+    int32_t* d_lead[2] = {nullptr, nullptr};
+    int64_t waves_cap[2] = {0, 0};
+    int32_t n_waves[2] = {0, 0};
+    int64_t* d_econst = nullptr;                             // [n_gc][2]
+    int32_t* d_rowcnt = nullptr;                             // scratch of the list build
+    int64_t rowcnt_cap = 0, lead_cap[2] = {0, 0}, econst_cap = 0;
 };
 
 static const char* kStatusText[] = {
@@ -513,6 +707,8 @@ static int check_config(const mpr_config* c)
     if (!(c->acc_target > 0.0 && c->acc_target < 1.0)) return MPR_EINVAL;
     if (!(c->T_min > 0.0) || !(c->T_max >= c->T_min) || !std::isfinite(c->T_max)) return MPR_EINVAL;
     if (c->tile_rows < -1 || c->grid_offset < 0) return MPR_EINVAL;
+    if (c->sweep_mode < MPR_SWEEP_AUTO || c->sweep_mode > MPR_SWEEP_SPARSE) return MPR_EINVAL;
+    if (c->sweep_mode == MPR_SWEEP_SPARSE && c->energy_prec == MPR_PREC_SINGLE) return MPR_EINVAL;
     return MPR_OK;
 }
 
@@ -530,6 +726,14 @@ static void free_device(mpr_ctx* c)
     c->d_acc = nullptr; c->d_zcopy = nullptr; c->d_e_part = nullptr; c->d_a_part = nullptr;
     c->d_trace = nullptr; c->d_flag = nullptr; c->d_ictl = nullptr; c->d_gacc = nullptr;
     c->trace_cap = 0;
+    void* lists[] = {c->d_sites, c->d_waves[0], c->d_waves[1], c->d_lead[0], c->d_lead[1],
+                     c->d_econst, c->d_rowcnt};
+    for (void* p : lists)
+        if (p) (void)hipFree(p);
+    c->d_sites = nullptr; c->d_waves[0] = c->d_waves[1] = nullptr;
+    c->d_lead[0] = c->d_lead[1] = nullptr; c->d_econst = nullptr; c->d_rowcnt = nullptr;
+    c->sites_cap = c->waves_cap[0] = c->waves_cap[1] = c->rowcnt_cap = 0;
+    c->lead_cap[0] = c->lead_cap[1] = c->econst_cap = 0;
     c->alloc_sig.clear();
 }
 
@@ -733,6 +937,154 @@ template <class S> static void launch_set_state(mpr_ctx* c, const double* u, con
     hipLaunchKernelGGL(k_set_state<S>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_state[c->cur], c->d_acc, u, acc, c->d_flag, mode);
 }
 
+// grow a device buffer to at least `bytes` (contents dropped); captured graphs hold the old
+// address, so they are dropped too
+static int ensure_buffer(mpr_ctx* c, void** p, int64_t* cap, int64_t bytes)
+{
+    if (*p && *cap >= bytes) return MPR_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    HIPCHK(c, hipMalloc(p, (size_t)std::max<int64_t>(bytes, 256)));
+    *cap = bytes;
+    return MPR_OK;
+}
+
+template <class S> static void launch_list_count(mpr_ctx* c, int hmax, const int64_t* row_off)
+{
+    hipLaunchKernelGGL(k_list_count<S>, dim3(hmax, 2 * c->G), dim3(256), 0, c->stream, c->d_gcs, c->C,
+                       c->d_state[c->cur], c->d_rowcnt, row_off);
+}
+
+template <class S>
+static void launch_list_fill(mpr_ctx* c, int hmax, const int64_t* row_off, const int64_t* base)
+{
+    hipLaunchKernelGGL(k_list_fill<S>, dim3(hmax, 2 * c->G), dim3(256), 0, c->stream, c->d_gcs, c->C,
+                       c->d_state[c->cur], c->d_rowcnt, row_off, base, c->d_sites);
+}
+
+template <class S, class F> static void launch_econst(mpr_ctx* c)
+{
+    int64_t plane = 0;
+    for (const auto& d : c->gcs) plane = std::max<int64_t>(plane, (int64_t)d.H * d.pitch);
+    const dim3 grid = site_grid(plane, (int)c->gcs.size(), 1024);
+    auto fn = c->cfg.boundary == MPR_PERIODIC ? k_econst<S, F, true> : k_econst<S, F, false>;
+    hipLaunchKernelGGL(fn, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_state[c->cur], c->cfg.q, c->d_econst);
+}
+
+// prediction-site lists of the compacted path, their waves, and the sample-sample bond energy
+static int build_lists(mpr_ctx* c)
+{
+    const int G = c->G, C = c->C, n_gc = (int)c->gcs.size();
+    std::vector<int64_t> meta(3 * G);                  // row offsets [G], list bases [2G]
+    int64_t rows = 0;
+    int hmax = 0;
+    for (int g = 0; g < G; ++g) {
+        meta[g] = rows;
+        rows += 2 * c->H[g];
+        hmax = std::max<int>(hmax, (int)c->H[g]);
+    }
+    // scratch: row counts [rows] | totals [2G] | meta (int64) [3G]
+    const int64_t meta_at = ((rows + 2 * G) * 4 + 7) / 8 * 8;
+    int rc = ensure_buffer(c, (void**)&c->d_rowcnt, &c->rowcnt_cap, meta_at + 3 * G * 8);
+    if (rc) return rc;
+    int32_t* d_tot = c->d_rowcnt + rows;
+    int64_t* d_meta = (int64_t*)((char*)c->d_rowcnt + meta_at);
+    HIPCHK(c, h2d(c, d_meta, meta.data(), G * sizeof(int64_t)));
+    switch (c->sprec) {
+    case MPR_FP64: launch_list_count<double>(c, hmax, d_meta); break;
+    case MPR_FP32: launch_list_count<float>(c, hmax, d_meta); break;
+    case MPR_FIX16: launch_list_count<Fix15>(c, hmax, d_meta); break;
+    default: launch_list_count<_Float16>(c, hmax, d_meta); break;
+    }
+    hipLaunchKernelGGL(k_list_scan, dim3(2 * G), dim3(256), 0, c->stream, c->d_gcs, C, c->d_rowcnt, d_meta, d_tot);
+    HIPCHK(c, hipGetLastError());
+    std::vector<int32_t> tot(2 * G);
+    HIPCHK(c, hipMemcpyAsync(tot.data(), d_tot, 2 * G * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // lists padded to whole waves (at least one per grid and colour, so every (grid, chain) has
+    // a lead wave in both launches)
+    int64_t entries = 0;
+    for (int i = 0; i < 2 * G; ++i) {
+        meta[G + i] = entries;
+        entries += std::max<int64_t>(1, (tot[i] + kWave - 1) / kWave) * kWave;
+    }
+    std::vector<int2> waves[2];
+    std::vector<int32_t> lead[2];
+    for (int col = 0; col < 2; ++col) {
+        lead[col].resize(n_gc);
+        for (int i = 0; i < n_gc; ++i) {
+            const int gr = c->gcs[i].grid;
+            const int64_t nw = std::max<int64_t>(1, ((int64_t)tot[2 * gr + col] + kWave - 1) / kWave);
+            lead[col][i] = (int32_t)waves[col].size();
+            for (int64_t w = 0; w < nw; ++w)
+                waves[col].push_back(int2{i, (int)(meta[G + 2 * gr + col] + w * kWave)});
+        }
+        if (waves[col].size() > (size_t)INT32_MAX / kWavesPerBlock)
+            return fail(c, MPR_EINVAL, "too many prediction sites for the compacted path");
+    }
+    if (entries > (int64_t)INT32_MAX) return fail(c, MPR_EINVAL, "too many prediction sites for the compacted path");
+    rc = ensure_buffer(c, (void**)&c->d_sites, &c->sites_cap, entries * 4);
+    if (rc) return rc;
+    HIPCHK(c, hipMemsetAsync(c->d_sites, 0xff, entries * 4, c->stream));
+    HIPCHK(c, h2d(c, d_meta + G, meta.data() + G, 2 * G * sizeof(int64_t)));
+    switch (c->sprec) {
+    case MPR_FP64: launch_list_fill<double>(c, hmax, d_meta, d_meta + G); break;
+    case MPR_FP32: launch_list_fill<float>(c, hmax, d_meta, d_meta + G); break;
+    case MPR_FIX16: launch_list_fill<Fix15>(c, hmax, d_meta, d_meta + G); break;
+    default: launch_list_fill<_Float16>(c, hmax, d_meta, d_meta + G); break;
+    }
+    for (int col = 0; col < 2; ++col) {
+        c->n_waves[col] = (int32_t)waves[col].size();
+        rc = ensure_buffer(c, (void**)&c->d_waves[col], &c->waves_cap[col], (int64_t)waves[col].size() * sizeof(int2));
+        if (rc) return rc;
+        rc = ensure_buffer(c, (void**)&c->d_lead[col], &c->lead_cap[col], (int64_t)n_gc * sizeof(int32_t));
+        if (rc) return rc;
+        HIPCHK(c, h2d(c, c->d_waves[col], waves[col].data(), waves[col].size() * sizeof(int2)));
+        HIPCHK(c, h2d(c, c->d_lead[col], lead[col].data(), n_gc * sizeof(int32_t)));
+    }
+    rc = ensure_buffer(c, (void**)&c->d_econst, &c->econst_cap, 2 * (int64_t)n_gc * sizeof(int64_t));
+    if (rc) return rc;
+    HIPCHK(c, hipMemsetAsync(c->d_econst, 0, 2 * n_gc * sizeof(int64_t), c->stream));
+    switch (c->sprec) {
+    case MPR_FP64: if (c->fsingle) launch_econst<double, float>(c); else launch_econst<double, double>(c); break;
+    case MPR_FP32: if (c->fsingle) launch_econst<float, float>(c); else launch_econst<float, double>(c); break;
+    case MPR_FIX16: launch_econst<Fix15, float>(c); break;
+    default: launch_econst<_Float16, float>(c); break;
+    }
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));      // host tables above go out of scope
+    return MPR_OK;
+}
+
+// the sweep path for the loaded data (sweep_mode, or the automatic rule)
+static int choose_path(mpr_ctx* c)
+{
+    bool possible = !c->esingle;
+    int64_t P = 0, N = 0;
+    for (int g = 0; g < c->G; ++g) {
+        const GcDesc& d = c->gcs[(size_t)g * c->C];
+        possible = possible && d.H < 65536 && d.pitch < 65536;
+        P += c->gi[g].n_pred;
+        N += c->H[g] * c->W[g];
+    }
+    const int mode = c->cfg.sweep_mode;
+    if (mode == MPR_SWEEP_SPARSE && !possible)
+        return fail(c, MPR_EINVAL, "the compacted sweep needs double-precision energy and sides below 65536");
+    const double frac = (double)P / (double)N, work = (double)N * c->C;
+    const bool prefer = c->fsingle ? (frac <= 0.4 && work <= 2097152.0)
+                                   : (frac <= 0.6 && work <= 33554432.0);
+    const bool sparse = mode == MPR_SWEEP_SPARSE || (mode == MPR_SWEEP_AUTO && possible && prefer);
+    if (sparse != c->sparse) {                 // graphs hold the other path's kernels
+        for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+        c->graphs.clear();
+    }
+    c->sparse = sparse;
+    return sparse ? build_lists(c) : MPR_OK;
+}
+
 extern "C" {
 
 void mpr_config_default(mpr_config* cfg)
@@ -875,6 +1227,8 @@ static int load_common(mpr_ctx* c, const double* z, const uint8_t* mask)
     c->next_sweep = 0;
     c->n_avg = 0;
     c->trace_len = 0;
+    int prc = choose_path(c);
+    if (prc) return prc;
     c->phase = PH_LOADED;
     if (c->cfg.tile_rows == -1) return autotune(c, 8, nullptr);
     return MPR_OK;
@@ -920,9 +1274,63 @@ static SweepFn sweep_fn(const mpr_ctx* c, int flags)
     }
 }
 
+static SparseFn sparse_fn(const mpr_ctx* c, int flags, int colour)
+{
+    const bool per = c->cfg.boundary == MPR_PERIODIC;
+    switch (c->sprec) {
+    case MPR_FP64: return c->fsingle ? pick_sparse<double, float>(flags, per, colour)
+                                     : pick_sparse<double, double>(flags, per, colour);
+    case MPR_FP32: return c->fsingle ? pick_sparse<float, float>(flags, per, colour)
+                                     : pick_sparse<float, double>(flags, per, colour);
+    case MPR_FIX16: return pick_sparse<Fix15, float>(flags, per, colour);
+    default: return pick_sparse<_Float16, float>(flags, per, colour);
+    }
+}
+
+// one sweep of the compacted path: colour 0 then colour 1, in place on the current buffer
+static void enqueue_sparse(mpr_ctx* c, int flags, int sweep_off, const RunCtl* run, uint8_t* dec)
+{
+    for (int col = 0; col < 2; ++col) {
+        SparseArgs a{};
+        a.sites = c->d_sites;
+        a.waves = c->d_waves[col];
+        a.lead_wave = c->d_lead[col];
+        a.gcs = c->d_gcs;
+        a.ctl = c->d_ctl;
+        a.run = run;
+        a.state = c->d_state[c->cur];
+        a.acc = c->d_acc;
+        a.dec = dec;
+        a.ictl = c->d_ictl;
+        a.gacc = c->d_gacc;
+        a.econst = c->d_econst;
+        a.trace = c->d_trace;
+        a.acc_target = c->cfg.acc_target;
+        a.T_min = c->cfg.T_min;
+        a.T_max = c->cfg.T_max;
+        a.q = c->cfg.q;
+        a.J = c->cfg.J;
+        a.n_gc = (int32_t)c->gcs.size();
+        a.n_waves = c->n_waves[col];
+        a.sweep_off = sweep_off;
+        a.key0 = (uint32_t)(c->cfg.seed & 0xffffffffu);
+        a.key1 = (uint32_t)(c->cfg.seed >> 32);
+        const unsigned blocks = (unsigned)((c->n_waves[col] + kWavesPerBlock - 1) / kWavesPerBlock);
+        hipLaunchKernelGGL(sparse_fn(c, flags, col), dim3(blocks), dim3(kWave * kWavesPerBlock), 0,
+                           c->stream, a);
+    }
+}
+
+// buffer flips per sweep: the fused path ping-pongs, the compacted path works in place
+static inline int flips(const mpr_ctx* c) { return c->sparse ? 0 : 1; }
+
 static void enqueue_sweep(mpr_ctx* c, int flags, int sweep_off, int src_buf, const RunCtl* run,
                           uint8_t* dec)
 {
+    if (c->sparse) {
+        enqueue_sparse(c, flags, sweep_off, run, dec);
+        return;
+    }
     SweepArgs a{};
     a.items = c->d_items;
     a.gcs = c->d_gcs;
@@ -969,7 +1377,7 @@ static void enqueue_block(mpr_ctx* c, int mode, int n)
     for (int i = 0; i < n; ++i) {
         enqueue_sweep(c, flags, i, buf, c->d_run, nullptr);
         if (mode == MODE_EQUIL && c->esingle) enqueue_control(c, i);   // else inside the sweeps
-        buf ^= 1;
+        buf ^= flips(c);
     }
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, c->stream, c->d_run, (int64_t)n);
 }
@@ -996,7 +1404,7 @@ static int run_sweeps(mpr_ctx* c, int mode, int n)
     }
     if (done < n) {
         enqueue_block(c, mode, n - done);
-        if ((n - done) & 1) c->cur ^= 1;
+        if ((n - done) & 1) c->cur ^= flips(c);
     }
     HIPCHK(c, hipGetLastError());
     c->next_sweep += n;
@@ -1019,7 +1427,8 @@ int mpr_infer_temperature(mpr_ctx* c, int32_t n_equil, double* T_host)
         c->graphs.clear();
     }
     hipLaunchKernelGGL(k_infer_begin, dim3((3 * n_gc * kAccCopies + 255) / 256), dim3(256), 0, c->stream, c->d_ctl,
-                       c->d_ictl, c->d_gacc, n_gc, c->cfg.J, c->cfg.T_min, c->cfg.T_max, c->d_run,
+                       c->d_ictl, c->d_gacc, c->sparse ? c->d_econst : nullptr, n_gc, c->cfg.J,
+                       c->cfg.T_min, c->cfg.T_max, c->d_run,
                        (int64_t)(c->next_sweep + n_equil / 2), (int64_t)c->next_sweep,
                        (int64_t)c->trace_cap, (int64_t)n_equil);
     rc = run_sweeps(c, MODE_EQUIL, n_equil);
@@ -1226,7 +1635,7 @@ int mpr_debug_sweep(mpr_ctx* c, int32_t sweep, uint8_t* dec)
     HIPCHK(c, hipMemsetAsync(dec, 0, (size_t)total, c->stream));
     hipLaunchKernelGGL(k_set_base, dim3(1), dim3(1), 0, c->stream, c->d_dbg_run, (int64_t)sweep);
     enqueue_sweep(c, F_DEC, 0, c->cur, c->d_dbg_run, dec);
-    c->cur ^= 1;
+    c->cur ^= flips(c);
     HIPCHK(c, hipGetLastError());
     return MPR_OK;
 }
@@ -1240,7 +1649,7 @@ int mpr_bench_sweeps(mpr_ctx* c, int32_t n)
     int buf = c->cur;
     for (int i = 0; i < n; ++i) {
         enqueue_sweep(c, F_ENERGY, i, buf, c->d_run, nullptr);
-        buf ^= 1;
+        buf ^= flips(c);
     }
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, c->stream, c->d_run, (int64_t)n);
     c->cur = buf;
@@ -1299,6 +1708,10 @@ static int use_rows(mpr_ctx* c, int rows)
 
 static int autotune(mpr_ctx* c, int n, int* best_out)
 {
+    if (c->sparse) {            // no work-item shape on the compacted path
+        if (best_out) *best_out = c->rows;
+        return MPR_OK;
+    }
     const std::string key = tune_key(c);
     auto& cache = tune_cache();
     auto hit = cache.find(key);
@@ -1362,6 +1775,14 @@ int mpr_autotune(mpr_ctx* c, int32_t n_sweeps, int32_t* rows_out)
     rc = autotune(c, n_sweeps, &best);
     if (rows_out) *rows_out = best;
     return rc;
+}
+
+int mpr_get_sweep_mode(mpr_ctx* c, int32_t* mode_out)
+{
+    if (!c || !mode_out) return MPR_EINVAL;
+    if (c->phase < PH_LOADED) return fail(c, MPR_ESTATE, "no data loaded");
+    *mode_out = c->sparse ? MPR_SWEEP_SPARSE : MPR_SWEEP_FUSED;
+    return MPR_OK;
 }
 
 int mpr_get_shape(mpr_ctx* c, int32_t* n_grids, int32_t* n_chains, int64_t* n_sites)

@@ -474,6 +474,53 @@ __device__ __forceinline__ double from_right(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Control state used by a sweep of (grid, chain) gc.  Frozen (ctl) outside an inference or when
+// the energy is summed in single precision; during an inference either applied here (apply:
+// the control step of the previous sweep from its exact sums, by every wave alike; the lead
+// wave stores the result, the trace entry, and resets the accumulator slot after next, whose
+// copy 0 starts at econst[gc] if given) or read as stored by the kernel that applied it.
+__device__ inline GcCtl sweep_control(bool fused, bool apply, int gc, const GcDesc& g, bool lead,
+                                      int lane, const GcCtl* ctl, const RunCtl* run, GcCtl* ictl,
+                                      int64_t* gacc, const int64_t* econst, double* trace,
+                                      int n_gc, int64_t s_abs, double J, double acc_target,
+                                      double T_min, double T_max, int& acc_slot)
+{
+    acc_slot = 0;
+    if (!fused) return ctl[gc];
+    const int64_t t = s_abs - run->trace_base;
+    const bool infer = (t >= 0) & (t < run->n_infer);
+    if (!infer) return ctl[gc];
+    const int tm = (int)t;
+    acc_slot = tm % 3;
+    if (!apply || tm == 0) return ictl[(tm & 1) * n_gc + gc];
+    GcCtl c = ictl[((tm - 1) & 1) * n_gc + gc];
+    const int64_t* A = gacc + ((int64_t)((tm - 1) % 3) * n_gc + gc) * kAccPerGc;
+    int64_t eh = 0, el = 0, na = 0;
+    if (lane < kAccCopies) {
+        eh = A[lane * kAccStride];
+        el = A[lane * kAccStride + 1];
+        na = A[lane * kAccStride + 2];
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        eh += __shfl_xor(eh, off, kWave);
+        el += __shfl_xor(el, off, kWave);
+        na += __shfl_xor(na, off, kWave);
+    }
+    double* tr = (lead && lane == 0) ? trace + ((int64_t)gc * run->trace_cap + (tm - 1)) * 4 : nullptr;
+    control_step(c, -J * fix2_value(eh, el) / (double)g.n_bonds, na, g.n_pred,
+                 s_abs - 1 >= run->s_half, J, acc_target, T_min, T_max, 0.0, false, tr);
+    if (lead) {
+        if (lane == 0) ictl[(tm & 1) * n_gc + gc] = c;
+        if (lane < kAccCopies) {
+            int64_t* z = gacc + ((int64_t)((tm + 1) % 3) * n_gc + gc) * kAccPerGc + lane * kAccStride;
+            z[0] = (econst && lane == 0) ? econst[2 * gc] : 0;
+            z[1] = (econst && lane == 0) ? econst[2 * gc + 1] : 0;
+            z[2] = 0;
+        }
+    }
+    return c;
+}
+
 // per-row data of one lane: (cos, sin) of both pair members, zero where the site is absent
 template <class F> struct RowCS { F c0, s0, c1, s1; };
 
@@ -501,45 +548,10 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
     // control state of this sweep: frozen, or (inference in double-precision energy) the
     // previous sweep's control step applied here from its exact sums
     constexpr bool FUSED = (FLAGS & F_ENERGY) && !ESINGLE;
-    GcCtl ctl;
     int acc_slot = 0;
-    if (FUSED) {
-        const int64_t t = s_abs - a.run->trace_base;
-        const bool infer = (t >= 0) & (t < a.run->n_infer);
-        const int tm = infer ? (int)t : 0;
-        acc_slot = tm % 3;
-        if (infer && tm > 0) {
-            ctl = a.ictl[((tm - 1) & 1) * a.n_gc + it.gc];
-            const int64_t* A = a.gacc + ((int64_t)((tm - 1) % 3) * a.n_gc + it.gc) * kAccPerGc;
-            int64_t eh = 0, el = 0, na = 0;
-            if (lane < kAccCopies) {
-                eh = A[lane * kAccStride];
-                el = A[lane * kAccStride + 1];
-                na = A[lane * kAccStride + 2];
-            }
-            for (int off = kWave / 2; off > 0; off >>= 1) {
-                eh += __shfl_xor(eh, off, kWave);
-                el += __shfl_xor(el, off, kWave);
-                na += __shfl_xor(na, off, kWave);
-            }
-            const bool lead = wid == g.item_begin;
-            double* tr = (lead && lane == 0) ? a.trace + ((int64_t)it.gc * a.run->trace_cap + (tm - 1)) * 4 : nullptr;
-            control_step(ctl, -a.J * fix2_value(eh, el) / (double)g.n_bonds, na, g.n_pred,
-                         s_abs - 1 >= a.run->s_half, a.J, a.acc_target, a.T_min, a.T_max, 0.0,
-                         false, tr);
-            if (lead) {
-                if (lane == 0) a.ictl[(tm & 1) * a.n_gc + it.gc] = ctl;
-                if (lane < kAccCopies) {
-                    int64_t* z = a.gacc + ((int64_t)((tm + 1) % 3) * a.n_gc + it.gc) * kAccPerGc + lane * kAccStride;
-                    z[0] = 0; z[1] = 0; z[2] = 0;
-                }
-            }
-        } else {
-            ctl = infer ? a.ictl[it.gc] : a.ctl[it.gc];
-        }
-    } else {
-        ctl = a.ctl[it.gc];
-    }
+    const GcCtl ctl = sweep_control(FUSED, true, it.gc, g, wid == g.item_begin, lane, a.ctl, a.run,
+                                    a.ictl, a.gacc, nullptr, a.trace, a.n_gc, s_abs, a.J,
+                                    a.acc_target, a.T_min, a.T_max, acc_slot);
 
     const F q = (F)a.q;
     const F J = (F)a.J;

@@ -1,0 +1,208 @@
+// mpr_sparse.hpp -- the compacted half-sweep for gfx950: one lane per prediction site of one
+// colour, so no lane work goes to sample sites.
+//
+// A sweep is two launches (colour 0, then colour 1) that update the state planes in place:
+// within a colour no site is a neighbour of another, so each lane reads the other plane and
+// writes only its own site.  The local field sums the four neighbours in the same order as the
+// fused row-window kernel ((left + right) + (up + down)), from the same stored values through
+// the same functions, and the site update and its Philox counter are shared, so both paths take
+// identical decisions from identical states.  The bond energy is split by bond kind: the
+// colour-1 launch sums the bonds of colour-1 prediction sites, the colour-0 launch the bonds
+// between colour-0 prediction sites and colour-1 samples, and the sample-sample bonds are a
+// constant of the data that seeds the accumulator.
+#pragma once
+
+#include "mpr_device.hpp"
+
+namespace mpr {
+
+constexpr uint32_t kNoSite = 0xFFFFFFFFu;        // list padding: the lane has no site
+
+struct SparseArgs {
+    const uint32_t* sites;     // this colour's site lists: (y << 16) | plane column, padded to 64
+    const int2* waves;         // per wave of 64 entries: (grid, chain), first entry of the wave
+    const int32_t* lead_wave;  // per (grid, chain): its first wave in this colour's list
+    const GcDesc* gcs;
+    const GcCtl* ctl;
+    const RunCtl* run;
+    void* state;               // state planes, updated in place
+    double* acc;
+    uint8_t* dec;
+    GcCtl* ictl;
+    int64_t* gacc;
+    const int64_t* econst;     // per (grid, chain): sample-sample bond energy, two fixed-point words
+    double* trace;
+    double acc_target, T_min, T_max, q, J;
+    int32_t n_gc, n_waves, sweep_off;
+    uint32_t key0, key1;
+};
+
+template <class St>
+__device__ __forceinline__ typename St::raw buf_load_one(Rsrc r, uint32_t off)
+{
+    using raw = typename St::raw;
+    if constexpr (sizeof(raw) == 8) {
+        const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+        return ((uint64_t)v.y << 32) | v.x;
+    } else if constexpr (sizeof(raw) == 4) {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+    } else {
+        return (raw)__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
+    }
+}
+
+template <class St>
+__device__ __forceinline__ void buf_store_one(Rsrc r, uint32_t off, typename St::raw v)
+{
+    using raw = typename St::raw;
+    if constexpr (sizeof(raw) == 8) {
+        u32x2_t w;
+        w.x = (uint32_t)v; w.y = (uint32_t)(v >> 32);
+        __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)off, 0, 0);
+    } else if constexpr (sizeof(raw) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)off, 0, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, r, (int)off, 0, 0);
+    }
+}
+
+// half-sweep of colour C over the listed prediction sites
+template <class S, class F, int FLAGS, bool PER, int C>
+__global__ __launch_bounds__(256) void k_sparse(SparseArgs a)
+{
+    using St = Store<S>;
+    using M = Math<F>;
+    using Raw = typename St::raw;
+    constexpr uint32_t kRaw = (uint32_t)sizeof(Raw);
+    constexpr bool FUSED = (FLAGS & F_ENERGY) != 0;   // this path sums energies in double precision
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6));
+    if (wid >= a.n_waves) return;                 // whole waves leave together
+    const int2 wv = a.waves[wid];
+    const int gc = __builtin_amdgcn_readfirstlane(wv.x);
+    const uint32_t ent = a.sites[(int64_t)wv.y + lane];
+    const GcDesc g = a.gcs[gc];
+    const int64_t s_abs = a.run->base_sweep + a.sweep_off;
+    const uint32_t sweep = (uint32_t)s_abs;
+
+    // colour 0 applies the previous sweep's control step; colour 1 reads what it stored
+    int acc_slot = 0;
+    const GcCtl ctl = sweep_control(FUSED, C == 0, gc, g, wid == a.lead_wave[gc], lane, a.ctl, a.run,
+                                    a.ictl, a.gacc, a.econst, a.trace, a.n_gc, s_abs, a.J,
+                                    a.acc_target, a.T_min, a.T_max, acc_slot);
+    const F q = (F)a.q;
+    const F J = (F)a.J;
+    const F inv_piq = (F)(1.0 / (3.14159265358979323846 * a.q));
+    const F alpha = (F)ctl.alpha;
+    const F kexp = (sizeof(F) == 4) ? (F)(-1.4426950408889634 / ctl.T) : (F)(-1.0 / ctl.T);
+
+    const int H = g.H, W = g.W, pitch = g.pitch;
+    const int plane_sz = H * pitch;
+    const bool valid = ent != kNoSite;
+    const int y = valid ? (int)(ent >> 16) : 0;
+    const int k = valid ? (int)(ent & 0xffffu) : 0;
+    const int x = 2 * k + ((y + C) & 1);
+    const Rsrc rs = make_rsrc((Raw*)a.state + g.plane_off, 2u * (uint32_t)plane_sz * kRaw);
+
+    // own site, and the four neighbours in the other plane (column = grid x >> 1)
+    const uint32_t own = (uint32_t)(C * plane_sz + y * pitch + k);
+    const Raw v = buf_load_one<St>(rs, valid ? own * kRaw : kBufOOB);
+    int xl = x - 1, xr = x + 1, yu = y - 1, yd = y + 1;
+    bool el = xl >= 0, er = xr < W, eu = yu >= 0, ed = yd < H;
+    if (PER) {
+        xl = el ? xl : xl + W; xr = er ? xr : xr - W;
+        yu = eu ? yu : yu + H; yd = ed ? yd : yd - H;
+        el = er = eu = ed = true;
+    }
+    el &= valid; er &= valid; eu &= valid; ed &= valid;
+    const int oc = (1 - C) * plane_sz;
+    const Raw rl = buf_load_one<St>(rs, el ? (uint32_t)(oc + y * pitch + (xl >> 1)) * kRaw : kBufOOB);
+    const Raw rr = buf_load_one<St>(rs, er ? (uint32_t)(oc + y * pitch + (xr >> 1)) * kRaw : kBufOOB);
+    const Raw ru = buf_load_one<St>(rs, eu ? (uint32_t)(oc + yu * pitch + (x >> 1)) * kRaw : kBufOOB);
+    const Raw rd = buf_load_one<St>(rs, ed ? (uint32_t)(oc + yd * pitch + (x >> 1)) * kRaw : kBufOOB);
+    F sl, cl, sr, cr, su, cu, sd, cd;
+    M::sincos_rev(q * St::template value<F>(rl), sl, cl);
+    M::sincos_rev(q * St::template value<F>(rr), sr, cr);
+    M::sincos_rev(q * St::template value<F>(ru), su, cu);
+    M::sincos_rev(q * St::template value<F>(rd), sd, cd);
+    cl = el ? cl : (F)0; sl = el ? sl : (F)0;
+    cr = er ? cr : (F)0; sr = er ? sr : (F)0;
+    cu = eu ? cu : (F)0; su = eu ? su : (F)0;
+    cd = ed ? cd : (F)0; sd = ed ? sd : (F)0;
+    const F Cf = (cl + cr) + (cu + cd);
+    const F Sf = (sl + sr) + (su + sd);
+
+    // the pair's counter; member k & 1 takes words (x, y) or (z, w)
+    const U4 r = philox10(U4{(uint32_t)(y * g.np + (k >> 1)), sweep, (uint32_t)g.chain_word, (uint32_t)C},
+                          a.key0, a.key1);
+    const uint32_t wa = (k & 1) ? r.z : r.x, wb = (k & 1) ? r.w : r.y;
+    const bool is_free = valid & !St::sample(v);
+    const SiteOut<S, F> o = hybrid_update<S, F>(St::template value<F>(v), is_free, Cf, Sf, q, inv_piq, J,
+                                                kexp, alpha, wa, wb);
+    const Raw nv = is_free ? St::template encode<F>(o.u) : v;
+    buf_store_one<St>(rs, is_free ? own * kRaw : kBufOOB, nv);
+
+    int n_acc = is_free ? ((o.dec >> 1) & 1) : 0;
+    int64_t e_hi = 0, e_lo = 0;
+    if (FLAGS & F_ENERGY) {
+        F e;
+        if (C == 1) {
+            e = M::fma(o.c, Cf, o.s * Sf);
+        } else {        // bonds to colour-1 samples only
+            const bool ml = el & St::sample(rl), mr = er & St::sample(rr);
+            const bool mu = eu & St::sample(ru), md = ed & St::sample(rd);
+            const F Cs = ((ml ? cl : (F)0) + (mr ? cr : (F)0)) + ((mu ? cu : (F)0) + (md ? cd : (F)0));
+            const F Ss = ((ml ? sl : (F)0) + (mr ? sr : (F)0)) + ((mu ? su : (F)0) + (md ? sd : (F)0));
+            e = M::fma(o.c, Cs, o.s * Ss);
+        }
+        const Fix2 f = fixed64x2(is_free ? (double)e : 0.0);
+        e_hi = f.hi;
+        e_lo = f.lo;
+    }
+    if (FLAGS & F_ACC) {
+        const Rsrc ra = make_rsrc(a.acc + g.plane_off, 2u * (uint32_t)plane_sz * 8u);
+        const uint32_t ao = is_free ? own * 8u : kBufOOB;
+        const u32x2_t p = __builtin_amdgcn_raw_buffer_load_b64(ra, (int)ao, 0, 0);
+        double d = __longlong_as_double((long long)(((uint64_t)p.y << 32) | p.x));
+        d += St::template value<double>(nv);
+        const uint64_t b = (uint64_t)__double_as_longlong(d);
+        u32x2_t w;
+        w.x = (uint32_t)b; w.y = (uint32_t)(b >> 32);
+        __builtin_amdgcn_raw_buffer_store_b64(w, ra, (int)ao, 0, 0);
+    }
+    if ((FLAGS & F_DEC) && is_free) a.dec[g.site_off + (int64_t)y * W + x] = (uint8_t)o.dec;
+
+    if (FUSED) {
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            n_acc += __shfl_xor(n_acc, off, kWave);
+            e_hi += __shfl_xor(e_hi, off, kWave);
+            e_lo += __shfl_xor(e_lo, off, kWave);
+        }
+        unsigned long long* A = (unsigned long long*)(a.gacc + ((int64_t)acc_slot * a.n_gc + gc) * kAccPerGc);
+        // a full block of one (grid, chain) adds once (block-uniform test)
+        const int b0 = (int)blockIdx.x * kWavesPerBlock;
+        const bool whole = (b0 + kWavesPerBlock <= a.n_waves) &&
+                           (a.waves[b0].x == a.waves[b0 + kWavesPerBlock - 1].x);
+        if (whole) {
+            __shared__ int64_t red[kWavesPerBlock][3];
+            const int w = (int)(threadIdx.x >> 6);
+            if (lane == 0) { red[w][0] = e_hi; red[w][1] = e_lo; red[w][2] = (int64_t)n_acc; }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int64_t s0 = 0, s1 = 0, s2 = 0;
+                for (int i = 0; i < kWavesPerBlock; ++i) { s0 += red[i][0]; s1 += red[i][1]; s2 += red[i][2]; }
+                A += (blockIdx.x & (kAccCopies - 1)) * kAccStride;
+                atomicAdd(A, (unsigned long long)s0);
+                atomicAdd(A + 1, (unsigned long long)s1);
+                atomicAdd(A + 2, (unsigned long long)s2);
+            }
+        } else if (lane == 0) {
+            A += (wid & (kAccCopies - 1)) * kAccStride;
+            atomicAdd(A, (unsigned long long)e_hi);
+            atomicAdd(A + 1, (unsigned long long)e_lo);
+            atomicAdd(A + 2, (unsigned long long)(int64_t)n_acc);
+        }
+    }
+}
+
+}  // namespace mpr

@@ -17,6 +17,7 @@ FP64, FP32, FP16, FIX16 = 0, 1, 2, 3
 PREC_DEFAULT, PREC_DOUBLE, PREC_SINGLE = -1, 0, 1
 OPEN, PERIODIC = 0, 1
 DEC_OR, DEC_ACCEPT, DEC_OUTSIDE = 1, 2, 4
+SWEEP_AUTO, SWEEP_FUSED, SWEEP_SPARSE = 0, 1, 2
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libmpr.so is not built (%s); run paper_1910_08448_amd/build.py" % LIB_PATH)
@@ -31,7 +32,8 @@ class mpr_config(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("alpha0", ctypes.c_double),
                 ("acc_target", ctypes.c_double), ("T_min", ctypes.c_double),
                 ("T_max", ctypes.c_double), ("tile_rows", ctypes.c_int32),
-                ("graph_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("graph_sweeps", ctypes.c_int32), ("sweep_mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class mpr_chain_stats(ctypes.Structure):
@@ -63,6 +65,7 @@ _SIG = {
     "mpr_bench_sweeps": (ctypes.c_int, [_vp, _i32]),
     "mpr_autotune": (ctypes.c_int, [_vp, _i32, _vp]),
     "mpr_get_shape": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "mpr_get_sweep_mode": (ctypes.c_int, [_vp, _vp]),
     "mpr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "mpr_last_error": (ctypes.c_char_p, [_vp]),
 }
@@ -161,6 +164,12 @@ class Context:
 
     def n_sites(self):
         return sum(h * w for h, w in self.shapes)
+
+    def sweep_mode(self):
+        """The sweep path chosen at the last load: SWEEP_FUSED or SWEEP_SPARSE."""
+        m = ctypes.c_int32()
+        self._chk(_lib.mpr_get_sweep_mode(self.h, ctypes.byref(m)), "mpr_get_sweep_mode")
+        return m.value
 
     def load(self, z, mask):
         """z: float64 CUDA tensor [H, W]; mask: uint8 CUDA tensor [H, W]."""

@@ -1,0 +1,123 @@
+"""Short text summaries of rocprofv3 CSV output for the sweep kernel.
+
+  python -m paper_1910_08448_amd.rocprof_summary stats DIR
+      kernel table (calls, average / min / max duration, share) from DIR/run_kernel_stats.csv
+  python -m paper_1910_08448_amd.rocprof_summary pmc DIR [DIR ...]
+      mean counter value per dispatch of the sweep kernels and of the copy probe
+  python -m paper_1910_08448_amd.rocprof_summary traffic KEY COPY_MIB FETCH_DIR WRITE_DIR [OUT]
+      HBM bytes per launch of the inference sweep kernel: FETCH_SIZE and WRITE_SIZE (KiB per
+      dispatch) each scaled by what the same counter read for the copy probe of COPY_MIB MiB
+      read + COPY_MIB MiB written; merged into OUT (JSON) under KEY (workload/precision)
+      together with a digest of the kernel sources, so a later kernel change voids the entry.
+
+The directories are rocprofv3 `--output-format csv -o run` output directories.
+"""
+import collections
+import csv
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in ("mpr_device.hpp", "mpr.hip"):
+        with open(os.path.join(ROOT, "paper_1910_08448_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _is_infer_sweep(name):
+    """The inference variant of the sweep kernel (energy sums, double-precision energy)."""
+    return "k_sweep" in name and ("1, false" in name or "Li1ELb0" in name)
+
+
+def _is_copy_probe(row):
+    return "copyBuffer" in row["Kernel_Name"] and int(row["Grid_Size"]) > 100000
+
+
+def stats(d, top=10):
+    rows = list(csv.DictReader(open(os.path.join(d, "run_kernel_stats.csv"))))
+    out = ["| kernel | calls | avg µs | min µs | max µs | % |", "|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        out.append("| `%s` | %s | %.2f | %.2f | %.2f | %.1f |" % (
+            r["Name"][:90], r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+            float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    return "\n".join(out)
+
+
+def _pmc_means(dirs):
+    agg = collections.defaultdict(list)
+    for d in dirs:
+        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+            if _is_copy_probe(r):
+                name = "copy probe"
+            elif "k_sweep" in r["Kernel_Name"]:
+                name = r["Kernel_Name"][:70]
+            else:
+                continue
+            agg[(name, r["Counter_Name"])].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in agg.items()}, {k: len(v) for k, v in agg.items()}
+
+
+def pmc(dirs):
+    means, counts = _pmc_means(dirs)
+    out = ["| kernel | counter | dispatches | mean per dispatch |", "|---|---|---|---|"]
+    for (k, c) in sorted(means):
+        out.append("| `%s` | %s | %d | %.6g |" % (k, c, counts[(k, c)], means[(k, c)]))
+    return "\n".join(out)
+
+
+def traffic(fetch_dir, write_dir, copy_mib):
+    res = {}
+    for d, ctr in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
+        sweep, probe = [], []
+        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+            if r["Counter_Name"] != ctr:
+                continue
+            if _is_copy_probe(r):
+                probe.append(float(r["Counter_Value"]))
+            elif _is_infer_sweep(r["Kernel_Name"]):
+                sweep.append(float(r["Counter_Value"]))
+        if not sweep or len(probe) != 1:
+            raise SystemExit("%s: %d sweep dispatches, %d copy probes" % (d, len(sweep), len(probe)))
+        factor = copy_mib * 1024.0 / probe[0]          # true KiB per counted KiB
+        kib = sum(sweep) / len(sweep)
+        res[ctr] = {"kib_per_dispatch": kib, "factor": factor, "dispatches": len(sweep),
+                    "bytes": kib * 1024.0 * factor}
+    return {"fetch": res["FETCH_SIZE"], "write": res["WRITE_SIZE"],
+            "bytes_per_launch": res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"]}
+
+
+def main(argv):
+    if len(argv) >= 2 and argv[0] == "stats":
+        print(stats(argv[1]))
+    elif len(argv) >= 2 and argv[0] == "pmc":
+        print(pmc(argv[1:]))
+    elif len(argv) >= 5 and argv[0] == "traffic":
+        key, copy_mib, fdir, wdir = argv[1], float(argv[2]), argv[3], argv[4]
+        entry = traffic(fdir, wdir, copy_mib)
+        if len(argv) >= 6:
+            out = argv[5]
+            doc = {}
+            if os.path.exists(out):
+                doc = json.load(open(out))
+            sha = kernel_source_sha()
+            if doc.get("kernel_source_sha") != sha:
+                doc = {"kernel_source_sha": sha, "entries": {}}
+            doc["entries"][key] = entry
+            with open(out, "w") as f:
+                json.dump(doc, f, indent=1, sort_keys=True)
+                f.write("\n")
+        print(json.dumps({key: entry}, indent=1))
+    else:
+        print(__doc__)
+        return 2
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))

@@ -45,10 +45,11 @@ def _gpu_ctx(mpr, z, mask, **cfg):
     return ctx
 
 
-def _decisions_case(mpr, H, W, boundary, n_chains, precision, seed, T=0.08, alpha=0.4, sweeps=3):
+def _decisions_case(mpr, H, W, boundary, n_chains, precision, seed, T=0.08, alpha=0.4, sweeps=3,
+                    mode=1):
     truth, z, mask = _field(H, W, seed)
     kw = dict(boundary=boundary, n_chains=n_chains, seed=seed + 5, alpha0=alpha)
-    ctx = _gpu_ctx(mpr, z, mask, precision=precision, **kw)
+    ctx = _gpu_ctx(mpr, z, mask, precision=precision, sweep_mode=mode, **kw)
     orc = O.Oracle(n_threads=2, **kw)
     orc.load(z, mask)
     u0 = synth.random_state(n_chains, mask, seed + 7)
@@ -57,12 +58,15 @@ def _decisions_case(mpr, H, W, boundary, n_chains, precision, seed, T=0.08, alph
     ctx.set_temperature(T)
     orc.set_temperature(T)
     out = []
+    before = (orc.get_state()["phi"] / TWO_PI).reshape(n_chains, H, W)   # samples included
     for s in range(sweeps):
         dg = ctx.debug_sweep(11 + s).cpu().numpy().reshape(n_chains, H, W)
         do = orc.debug_sweep(11 + s)
         ug = ctx.get_state()["u"].cpu().numpy().reshape(n_chains, H, W)
         uo = orc.get_state()["phi"] / TWO_PI
         out.append((dg, do, ug, uo))
+        _LAST_BEFORE.append(before)
+        before = uo.reshape(n_chains, H, W)
         # continue both from the oracle's state so each sweep is compared from identical input
         ctx.set_state(u=_dev(uo.reshape(-1), torch.float64))
     return mask, out
@@ -81,6 +85,62 @@ def test_fp64_decisions_and_angles_match_oracle(mpr, H, W, boundary, chains):
         agree = free & (dg == do)
         assert np.abs(ug - uo)[agree].max() <= 1e-9
         assert np.array_equal(ug[~free] * 0, uo[~free] * 0)
+
+
+_LAST_BEFORE = []
+
+
+def _degenerate_sites(mask, before, after, boundary):
+    """Free sites whose local field vanishes up to rounding (|C| + |S| < 1e-12), and the colour-1
+    sites next to a degenerate colour-0 site.  The field of neighbours at exactly half a turn
+    apart (the extreme samples map to 0 and 1) is exactly zero in turns, where the device
+    evaluates it, but sin of the radian angle fl(pi) is 1.2e-16, so the two sides may take
+    different (each valid) over-relaxation decisions there; elsewhere they must agree."""
+    C, H, W = before.shape
+    bad = np.zeros((C, H, W), bool)
+    for ch in range(C):
+        for y in range(H):
+            for x in range(W):
+                if mask[y, x]:
+                    continue
+                phi = TWO_PI * (before[ch] if (x + y) % 2 == 0 else after[ch])
+                c, s = O.local_field(np.ascontiguousarray(phi), y, x, boundary=boundary)
+                if abs(c) + abs(s) < 1e-12:
+                    bad[ch, y, x] = True
+        for y in range(H):
+            for x in range(W):
+                if bad[ch, y, x] and (x + y) % 2 == 0:
+                    for dy, dx in ((0, 1), (0, -1), (1, 0), (-1, 0)):
+                        yy, xx = y + dy, x + dx
+                        if boundary:
+                            yy, xx = yy % H, xx % W
+                        if 0 <= yy < H and 0 <= xx < W:
+                            bad[ch, yy, xx] = True
+    return bad
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("H,W,boundary,chains", [
+    (2, 2, 0, 1), (3, 2, 0, 1), (2, 3, 0, 2), (5, 7, 0, 1), (2, 4, 1, 1), (4, 8, 1, 2),
+    (6, 4, 1, 1), (1 + 2 * 60, 9, 0, 1), (3, 4 * 60 + 3, 0, 1)])
+def test_fp64_tiny_and_ragged_grids_match_oracle(mpr, H, W, boundary, chains, mode):
+    """Degenerate shapes: the smallest grids (open and periodic, where the row window wraps
+    onto itself), one-pair-wide and one-work-item-tall strips, and sides one past a work
+    item's 60 lane pairs.  Every decision and angle agrees except where the local field
+    vanishes (see _degenerate_sites)."""
+    _LAST_BEFORE.clear()
+    mask, rounds = _decisions_case(mpr, H, W, boundary, chains, mpr.FP64, seed=H * 7 + W + 100,
+                                   mode=mode)
+    free = np.broadcast_to(mask == 0, rounds[0][0].shape)
+    n_checked = 0
+    for (dg, do, ug, uo), before in zip(rounds, _LAST_BEFORE):
+        uo = uo.reshape(dg.shape)
+        assert np.array_equal(dg[~free], do[~free]) and not dg[~free].any()
+        ok = free & ~_degenerate_sites(mask, before, uo, boundary)
+        assert np.array_equal(dg[ok], do[ok])
+        assert np.allclose(ug[ok], uo[ok], rtol=0, atol=1e-9)
+        n_checked += int(ok.sum())
+    assert n_checked > 0
 
 
 def test_fp64_trace_matches_oracle(mpr):
@@ -121,12 +181,13 @@ def test_fp64_predictions_match_oracle_grid64(mpr, p):
     assert np.array_equal(zg[~m], w["z"][~m])
 
 
-def test_predictions_invariant_to_tiles_and_graphs(mpr):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_predictions_invariant_to_tiles_and_graphs(mpr, mode):
     w = synth.workload("grid64")
     res = []
     for tile_rows, graph in [(16, 0), (64, 0), (16, -1), (8, 4)]:
         ctx = _gpu_ctx(mpr, w["z"], w["mask"], seed=3, precision=mpr.FP32, tile_rows=tile_rows,
-                       graph_sweeps=graph, n_chains=2)
+                       graph_sweeps=graph, n_chains=2, sweep_mode=mode)
         ctx.infer_temperature(40)
         ctx.run(10)
         res.append(ctx.predictions().cpu().numpy())
@@ -143,7 +204,7 @@ def test_batch_equals_single_grids(mpr):
         H, W = int(rng.integers(9, 140)), int(rng.integers(9, 140))
         truth, z, mask = _field(H, W, 50 + g, p=float(rng.uniform(0.2, 0.7)))
         grids.append((z, mask))
-    kw = dict(seed=77, n_chains=2, precision=mpr.FP32)
+    kw = dict(seed=77, n_chains=2, precision=mpr.FP32, sweep_mode=mpr.SWEEP_FUSED)
     b = mpr.Context(shapes=[z.shape for z, _ in grids], stream=torch.cuda.Stream(), **kw)
     b.batch_load(_dev(np.concatenate([z.ravel() for z, _ in grids]), torch.float64),
                  _dev(np.concatenate([m.ravel() for _, m in grids]), torch.uint8))
@@ -185,9 +246,10 @@ def test_batch_fp64_matches_oracle_per_grid(mpr):
         off += z.size
 
 
-def test_resume_is_bitwise_on_gpu(mpr):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_resume_is_bitwise_on_gpu(mpr, mode):
     w = synth.workload("grid64")
-    kw = dict(seed=9, n_chains=2, precision=mpr.FP16)
+    kw = dict(seed=9, n_chains=2, precision=mpr.FP16, sweep_mode=mode)
     A = _gpu_ctx(mpr, w["z"], w["mask"], **kw)
     A.infer_temperature(50)
     A.run(30)
@@ -282,7 +344,8 @@ def test_autotune_keeps_results(mpr):
     w = synth.workload("grid64")
     res = []
     for tune in (False, True):
-        ctx = _gpu_ctx(mpr, w["z"], w["mask"], seed=5, precision=mpr.FP32, n_chains=2)
+        ctx = _gpu_ctx(mpr, w["z"], w["mask"], seed=5, precision=mpr.FP32, n_chains=2,
+                       sweep_mode=mpr.SWEEP_FUSED)
         if tune:
             rows = ctx.autotune(4)
             assert rows >= 2
@@ -292,11 +355,13 @@ def test_autotune_keeps_results(mpr):
     assert np.array_equal(res[0], res[1])
 
 
-def test_large_grid_trace_matches_oracle(mpr):
-    """Inference trace on a 512 x 1000 grid: several column strips and row blocks per chain."""
+@pytest.mark.parametrize("mode", [1, 2])
+def test_large_grid_trace_matches_oracle(mpr, mode):
+    """Inference trace on a 512 x 1000 grid: several column strips and row blocks per chain
+    (fused path), several thousand waves per colour (compacted path)."""
     truth, z, mask = _field(512, 1000, 9)
     kw = dict(seed=31, n_chains=1)
-    ctx = _gpu_ctx(mpr, z, mask, **kw)
+    ctx = _gpu_ctx(mpr, z, mask, sweep_mode=mode, **kw)
     orc = O.Oracle(n_threads=8, **kw)
     orc.load(z, mask)
     Tg = ctx.infer_temperature(24)
@@ -347,3 +412,106 @@ def test_precision_settings(mpr, name):
     mae_o = np.abs(zo - w["truth"])[m].mean()
     mae_g = np.abs(zg - w["truth"])[m].mean()
     assert abs(mae_g / mae_o - 1) <= 0.01, (mae_g, mae_o)
+
+
+# ---------------------------------------------------------------- compacted (sparse) sweep path
+@pytest.mark.parametrize("H,W,boundary,chains", [
+    (64, 64, 0, 1), (37, 53, 0, 2), (16, 24, 1, 1), (2, 2, 0, 1), (2, 4, 1, 1), (3, 243, 0, 1),
+    (130, 244, 0, 1)])
+def test_sparse_fp64_decisions_and_angles_match_oracle(mpr, H, W, boundary, chains):
+    """The compacted path takes the oracle's decisions from identical states."""
+    mask, rounds = _decisions_case(mpr, H, W, boundary, chains, mpr.FP64, seed=H * 13 + W,
+                                   mode=mpr.SWEEP_SPARSE)
+    free = np.broadcast_to(mask == 0, rounds[0][0].shape)
+    for dg, do, ug, uo in rounds:
+        assert np.array_equal(dg[~free], do[~free]) and not dg[~free].any()
+        assert (dg == do)[free].mean() >= 0.99999
+        assert np.allclose(ug, uo, rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2, 3])
+def test_sparse_and_fused_decisions_are_identical(mpr, precision):
+    """Same field arithmetic, functions and counters: bitwise-equal decisions and angles from
+    identical states, in every storage precision."""
+    H, W = 45, 70
+    truth, z, mask = _field(H, W, 99)
+    u0 = synth.random_state(2, mask, 5)
+    out = []
+    for mode in (mpr.SWEEP_FUSED, mpr.SWEEP_SPARSE):
+        ctx = _gpu_ctx(mpr, z, mask, precision=precision, sweep_mode=mode, n_chains=2, seed=3,
+                       alpha0=0.5)
+        assert ctx.sweep_mode() == mode
+        ctx.set_state(u=_dev(u0.reshape(-1), torch.float64))
+        ctx.set_temperature(0.05)
+        decs = [ctx.debug_sweep(s).cpu().numpy() for s in (4, 5, 6)]
+        out.append((decs, ctx.get_state()["u"].cpu().numpy()))
+    for a, b in zip(out[0][0], out[1][0]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(out[0][1], out[1][1])
+
+
+def test_sparse_trace_matches_oracle(mpr):
+    truth, z, mask = _field(48, 64, 17)
+    kw = dict(seed=21, n_chains=2)
+    ctx = _gpu_ctx(mpr, z, mask, sweep_mode=mpr.SWEEP_SPARSE, **kw)
+    orc = O.Oracle(n_threads=4, **kw)
+    orc.load(z, mask)
+    Tg = ctx.infer_temperature(40)
+    To = orc.infer_temperature(40)
+    for ch in range(2):
+        tg, to = ctx.trace(ch), orc.trace(ch)
+        assert np.allclose(tg, to, rtol=1e-9, atol=1e-13), np.abs(tg - to).max(axis=0)
+    assert np.allclose(Tg, To, rtol=1e-9)
+
+
+@pytest.mark.parametrize("p", [0.33, 0.66])
+def test_sparse_predictions_match_oracle_grid64(mpr, p):
+    w = synth.workload("grid64", p_missing=p)
+    kw = dict(seed=w["mc_seed"], n_chains=2)
+    zo, To = O.predict(w["z"], w["mask"], 256, 100, n_threads=4, **kw)
+    ctx = _gpu_ctx(mpr, w["z"], w["mask"], sweep_mode=mpr.SWEEP_SPARSE, **kw)
+    Tg = ctx.infer_temperature(256)
+    ctx.run(100)
+    zg = ctx.predictions().cpu().numpy().reshape(64, 64)
+    rng = np.nanmax(w["z"]) - np.nanmin(w["z"])
+    assert np.allclose(Tg, To, rtol=1e-8)
+    assert np.abs(zg - zo).mean() <= 1e-3 * rng
+
+
+def test_sparse_batch_equals_single_grids(mpr):
+    shapes = [(40, 56), (33, 17), (64, 64)]
+    fields = [_field(h, w, 300 + i) for i, (h, w) in enumerate(shapes)]
+    kw = dict(seed=8, n_chains=2, sweep_mode=mpr.SWEEP_SPARSE)
+    bctx = mpr.Context(shapes=shapes, stream=torch.cuda.Stream(), **kw)
+    bctx.batch_load(_dev(np.concatenate([f[1].ravel() for f in fields]), torch.float64),
+                    _dev(np.concatenate([f[2].ravel() for f in fields]), torch.uint8))
+    bctx.infer_temperature(30)
+    bctx.run(10)
+    zb = bctx.predictions().cpu().numpy()
+    off = 0
+    for i, (h, w) in enumerate(shapes):
+        ctx = _gpu_ctx(mpr, fields[i][1], fields[i][2], grid_offset=i, **kw)
+        ctx.infer_temperature(30)
+        ctx.run(10)
+        zs = ctx.predictions().cpu().numpy()
+        assert np.array_equal(zs, zb[off:off + h * w])
+        off += h * w
+
+
+def test_automatic_path_choice(mpr):
+    """AUTO takes the compacted path for small grids with few prediction sites (at most 40 %
+    with single-precision functions, 60 % with double), when the energy is summed in double
+    precision; the fused path otherwise."""
+    for p, prec, esingle, want in [(0.33, mpr.FP32, False, mpr.SWEEP_SPARSE),
+                                   (0.5, mpr.FP32, False, mpr.SWEEP_FUSED),
+                                   (0.5, mpr.FP64, False, mpr.SWEEP_SPARSE),
+                                   (0.9, mpr.FP64, False, mpr.SWEEP_FUSED),
+                                   (0.33, mpr.FP32, True, mpr.SWEEP_FUSED)]:
+        truth, z, mask = _field(64, 64, 5, p=p)
+        ctx = _gpu_ctx(mpr, z, mask, precision=prec,
+                       energy_prec=mpr.PREC_SINGLE if esingle else mpr.PREC_DEFAULT)
+        assert ctx.sweep_mode() == want, (p, prec, esingle)
+    truth, z, mask = _field(64, 64, 5)
+    with pytest.raises(mpr.MprError):
+        _gpu_ctx(mpr, z, mask, precision=mpr.FP32, energy_prec=mpr.PREC_SINGLE,
+                 sweep_mode=mpr.SWEEP_SPARSE)
