@@ -521,6 +521,30 @@ __device__ inline GcCtl sweep_control(bool fused, bool apply, int gc, const GcDe
     return c;
 }
 
+// Exact wave sum of a 32-bit integer whose total fits in 32 bits: DPP row shifts then row
+// broadcasts (plain VALU moves, no LDS round trip); lane 63 ends with the total, returned
+// wave-uniform.
+__device__ __forceinline__ int wave_sum_i32(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15 -> rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31 -> rows 2, 3
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Exact wave sum of a 64-bit integer of magnitude below 2^57 per lane: three 21-bit limbs
+// (x = a 2^42 + b 2^21 + c, 0 <= b, c < 2^21), each limb's wave total fits in 32 bits.
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t x)
+{
+    const int c = (int)(x & 0x1FFFFF);
+    const int b = (int)((x >> 21) & 0x1FFFFF);
+    const int a = (int)(x >> 42);
+    return ((int64_t)wave_sum_i32(a) << 42) + ((int64_t)wave_sum_i32(b) << 21) + (int64_t)wave_sum_i32(c);
+}
+
 // per-row data of one lane: (cos, sin) of both pair members, zero where the site is absent
 template <class F> struct RowCS { F c0, s0, c1, s1; };
 
@@ -840,13 +864,17 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
 
 #endif
 
-    // wave reductions -> per-item partials (exact integers, or a fixed-order float tree)
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        n_acc += __shfl_xor(n_acc, off, kWave);
-        if (FLAGS & F_ENERGY) {
-            if (ESINGLE) e_flt += __shfl_xor(e_flt, off, kWave);
-            else { e_hi += __shfl_xor(e_hi, off, kWave); e_lo += __shfl_xor(e_lo, off, kWave); }
+    // wave reductions (inference sweeps only): exact integer sums, or a fixed-order float tree
+    if (!(FLAGS & F_ENERGY)) return;
+    if (ESINGLE) {
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            n_acc += __shfl_xor(n_acc, off, kWave);
+            e_flt += __shfl_xor(e_flt, off, kWave);
         }
+    } else {
+        n_acc = wave_sum_i32(n_acc);
+        e_hi = wave_sum_i64(e_hi);
+        e_lo = wave_sum_i64(e_lo);
     }
     if (FUSED) {
         unsigned long long* A = (unsigned long long*)(a.gacc + ((int64_t)acc_slot * a.n_gc + it.gc) * kAccPerGc);

@@ -173,11 +173,9 @@ __global__ __launch_bounds__(256) void k_sparse(SparseArgs a)
     if ((FLAGS & F_DEC) && is_free) a.dec[g.site_off + (int64_t)y * W + x] = (uint8_t)o.dec;
 
     if (FUSED) {
-        for (int off = kWave / 2; off > 0; off >>= 1) {
-            n_acc += __shfl_xor(n_acc, off, kWave);
-            e_hi += __shfl_xor(e_hi, off, kWave);
-            e_lo += __shfl_xor(e_lo, off, kWave);
-        }
+        n_acc = wave_sum_i32(n_acc);
+        e_hi = wave_sum_i64(e_hi);
+        e_lo = wave_sum_i64(e_lo);
         unsigned long long* A = (unsigned long long*)(a.gacc + ((int64_t)acc_slot * a.n_gc + gc) * kAccPerGc);
         // a full block of one (grid, chain) adds once (block-uniform test)
         const int b0 = (int)blockIdx.x * kWavesPerBlock;
