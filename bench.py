@@ -55,7 +55,7 @@ def kernel_source_sha():
     """Digest of the sources the sweep kernel is built from."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("mpr_device.hpp", "mpr.hip"):
+    for f in ("mpr_device.hpp", "mpr_sparse.hpp", "mpr.hip"):
         with open(os.path.join(ROOT, "paper_1910_08448_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

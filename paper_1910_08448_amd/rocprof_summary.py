@@ -24,15 +24,23 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def kernel_source_sha():
     h = hashlib.sha256()
-    for f in ("mpr_device.hpp", "mpr.hip"):
+    for f in ("mpr_device.hpp", "mpr_sparse.hpp", "mpr.hip"):
         with open(os.path.join(ROOT, "paper_1910_08448_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def _is_infer_sweep(name):
-    """The inference variant of the sweep kernel (energy sums, double-precision energy)."""
-    return "k_sweep" in name and ("1, false" in name or "Li1ELb0" in name)
+def _infer_sweep_kind(name):
+    """Which inference-sweep kernel a dispatch is: 'fused' (k_sweep with energy sums in double
+    precision), 'sparse0' / 'sparse1' (the compacted path's colour kernels), or None."""
+    if "k_sweep" in name and ("1, false" in name or "Li1ELb0" in name):
+        return "fused"
+    if "k_sparse" in name:
+        for c in (0, 1):
+            if ", 1, false, %d>" % c in name or ", 1, true, %d>" % c in name or \
+               "Li1ELb0ELi%dE" % c in name or "Li1ELb1ELi%dE" % c in name:
+                return "sparse%d" % c
+    return None
 
 
 def _is_copy_probe(row):
@@ -55,7 +63,7 @@ def _pmc_means(dirs):
         for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
             if _is_copy_probe(r):
                 name = "copy probe"
-            elif "k_sweep" in r["Kernel_Name"]:
+            elif "k_sweep" in r["Kernel_Name"] or "k_sparse" in r["Kernel_Name"]:
                 name = r["Kernel_Name"][:70]
             else:
                 continue
@@ -72,22 +80,26 @@ def pmc(dirs):
 
 
 def traffic(fetch_dir, write_dir, copy_mib):
+    """Per inference sweep: the fused kernel's dispatch, or the two colour kernels of the
+    compacted path added."""
     res = {}
     for d, ctr in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
-        sweep, probe = [], []
+        kinds, probe = collections.defaultdict(list), []
         for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
             if r["Counter_Name"] != ctr:
                 continue
             if _is_copy_probe(r):
                 probe.append(float(r["Counter_Value"]))
-            elif _is_infer_sweep(r["Kernel_Name"]):
-                sweep.append(float(r["Counter_Value"]))
-        if not sweep or len(probe) != 1:
-            raise SystemExit("%s: %d sweep dispatches, %d copy probes" % (d, len(sweep), len(probe)))
+            else:
+                k = _infer_sweep_kind(r["Kernel_Name"])
+                if k:
+                    kinds[k].append(float(r["Counter_Value"]))
+        if not kinds or len(probe) != 1:
+            raise SystemExit("%s: %d sweep kernels, %d copy probes" % (d, len(kinds), len(probe)))
         factor = copy_mib * 1024.0 / probe[0]          # true KiB per counted KiB
-        kib = sum(sweep) / len(sweep)
-        res[ctr] = {"kib_per_dispatch": kib, "factor": factor, "dispatches": len(sweep),
-                    "bytes": kib * 1024.0 * factor}
+        kib = sum(sum(v) / len(v) for v in kinds.values())
+        res[ctr] = {"kib_per_sweep": kib, "factor": factor, "kernels": sorted(kinds),
+                    "dispatches": sum(len(v) for v in kinds.values()), "bytes": kib * 1024.0 * factor}
     return {"fetch": res["FETCH_SIZE"], "write": res["WRITE_SIZE"],
             "bytes_per_launch": res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"]}
 
