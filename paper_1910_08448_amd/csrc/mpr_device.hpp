@@ -521,6 +521,18 @@ __device__ inline GcCtl sweep_control(bool fused, bool apply, int gc, const GcDe
     return c;
 }
 
+// XCD-aware block order: the dispatcher hands block b to XCD b % 8, each XCD with its own L2, so
+// logical block numbers are dealt out in 8 contiguous runs, one per XCD.  Neighbouring work
+// (adjacent row blocks, adjacent list entries) then shares one L2, and halo rows are fetched
+// once per XCD instead of once per neighbour.  A bijection on [0, nb) for any nb.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int xcd = b % kXcds, local = b / kXcds;
+    const int per = nb / kXcds, rem = nb % kXcds;
+    return xcd * per + (xcd < rem ? xcd : rem) + local;
+}
+
 // Exact wave sum of a 32-bit integer whose total fits in 32 bits: DPP row shifts then row
 // broadcasts (plain VALU moves, no LDS round trip); lane 63 ends with the total, returned
 // wave-uniform.
@@ -562,7 +574,8 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
     using M = Math<F>;
     using Pair = typename St::pair;
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6));
+    const int lblock = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int wid = __builtin_amdgcn_readfirstlane(lblock * kWavesPerBlock + (int)(threadIdx.x >> 6));
     if (wid >= a.n_items) return;                 // whole waves leave together
     const Item it = a.items[wid];
     const GcDesc g = a.gcs[it.gc];
@@ -880,7 +893,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
         unsigned long long* A = (unsigned long long*)(a.gacc + ((int64_t)acc_slot * a.n_gc + it.gc) * kAccPerGc);
         // a full block of one (grid, chain) adds once (block-uniform test: every wave of the
         // block takes the same branch, so all or none reach the barrier)
-        const int b0 = (int)blockIdx.x * kWavesPerBlock;
+        const int b0 = lblock * kWavesPerBlock;
         const bool whole = (b0 + kWavesPerBlock <= a.n_items) &&
                            (a.items[b0].gc == a.items[b0 + kWavesPerBlock - 1].gc);
         if (whole) {

@@ -76,7 +76,8 @@ __global__ __launch_bounds__(256) void k_sparse(SparseArgs a)
     constexpr uint32_t kRaw = (uint32_t)sizeof(Raw);
     constexpr bool FUSED = (FLAGS & F_ENERGY) != 0;   // this path sums energies in double precision
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6));
+    const int lblock = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int wid = __builtin_amdgcn_readfirstlane(lblock * kWavesPerBlock + (int)(threadIdx.x >> 6));
     if (wid >= a.n_waves) return;                 // whole waves leave together
     const int2 wv = a.waves[wid];
     const int gc = __builtin_amdgcn_readfirstlane(wv.x);
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(256) void k_sparse(SparseArgs a)
         e_lo = wave_sum_i64(e_lo);
         unsigned long long* A = (unsigned long long*)(a.gacc + ((int64_t)acc_slot * a.n_gc + gc) * kAccPerGc);
         // a full block of one (grid, chain) adds once (block-uniform test)
-        const int b0 = (int)blockIdx.x * kWavesPerBlock;
+        const int b0 = lblock * kWavesPerBlock;
         const bool whole = (b0 + kWavesPerBlock <= a.n_waves) &&
                            (a.waves[b0].x == a.waves[b0 + kWavesPerBlock - 1].x);
         if (whole) {
