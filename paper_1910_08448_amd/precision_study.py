@@ -59,7 +59,11 @@ def main():
             ctx.batch_load(z, mask)
             ctx.infer_temperature(args.n_equil, want_T=False)
             ctx.run(args.n_avg)
-            return ctx.predictions()
+            zh = ctx.predictions()
+        # the caller reads the predictions on its own stream
+        torch.cuda.current_stream().wait_stream(stream)
+        zh.record_stream(torch.cuda.current_stream())
+        return zh
 
     out = {"n_equil": args.n_equil, "n_avg": args.n_avg, "missing": 0.9, "kappa": 0.2,
            "speedup": {}, "accuracy": {}}
@@ -99,6 +103,8 @@ def main():
         for name in SETTINGS:
             zh = predict(z, m, name, 9000 + r, cache)
             aae[name].append(float((zh[pm] - z_true.flatten()[pm]).abs().mean()))
+        if (r + 1) % 10 == 0:
+            print("[study] accuracy: %d of %d realisations" % (r + 1, args.M), file=sys.stderr, flush=True)
     for c in cache.values():
         c.close()
     base = np.array(aae["DDD"])
