@@ -515,3 +515,60 @@ def test_automatic_path_choice(mpr):
     with pytest.raises(mpr.MprError):
         _gpu_ctx(mpr, z, mask, precision=mpr.FP32, energy_prec=mpr.PREC_SINGLE,
                  sweep_mode=mpr.SWEEP_SPARSE)
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_other_q_and_J_match_oracle(mpr, mode):
+    """q < 1/2 and J != 1 (Eq. (2)): decisions from identical states and the inference trace."""
+    truth, z, mask = _field(40, 52, 61)
+    kw = dict(q=0.3, J=1.7, seed=12, n_chains=1)
+    ctx = _gpu_ctx(mpr, z, mask, sweep_mode=mode, alpha0=0.5, **kw)
+    orc = O.Oracle(n_threads=2, alpha0=0.5, **kw)
+    orc.load(z, mask)
+    u0 = synth.random_state(1, mask, 3)
+    ctx.set_state(u=_dev(u0.reshape(-1), torch.float64))
+    orc.set_state(phi=TWO_PI * u0)
+    ctx.set_temperature(0.1)
+    orc.set_temperature(0.1)
+    dg = ctx.debug_sweep(2).cpu().numpy().reshape(1, 40, 52)
+    do = orc.debug_sweep(2)
+    free = np.broadcast_to(mask == 0, dg.shape)
+    assert (dg == do)[free].mean() >= 0.99999
+    ctx = _gpu_ctx(mpr, z, mask, sweep_mode=mode, **kw)
+    orc = O.Oracle(n_threads=2, **kw)
+    orc.load(z, mask)
+    Tg = ctx.infer_temperature(30)
+    To = orc.infer_temperature(30)
+    assert np.allclose(ctx.trace(0), orc.trace(0), rtol=1e-9, atol=1e-13)
+    assert np.allclose(Tg, To, rtol=1e-9)
+
+
+def test_sparse_colour_without_prediction_sites(mpr):
+    """A grid whose colour-0 sites are all samples: that colour's list is one padding wave, and
+    the compacted path still matches the oracle's trace and the fused path's decisions."""
+    H, W = 30, 44
+    truth = synth.gaussian_field(H, W, 0.5, 8.0, 50.0, 10.0, 71)
+    yy, xx = np.mgrid[0:H, 0:W]
+    rng = np.random.default_rng(3)
+    mask = np.ones((H, W), np.uint8)
+    odd = (yy + xx) % 2 == 1
+    mask[odd & (rng.random((H, W)) < 0.5)] = 0          # only colour-1 sites are missing
+    z = np.where(mask == 1, truth, np.nan)
+    kw = dict(seed=5, n_chains=2)
+    ctx = _gpu_ctx(mpr, z, mask, sweep_mode=mpr.SWEEP_SPARSE, **kw)
+    orc = O.Oracle(n_threads=2, **kw)
+    orc.load(z, mask)
+    Tg = ctx.infer_temperature(20)
+    To = orc.infer_temperature(20)
+    for ch in range(2):
+        assert np.allclose(ctx.trace(ch), orc.trace(ch), rtol=1e-9, atol=1e-13)
+    assert np.allclose(Tg, To, rtol=1e-9)
+    ctx.run(5)
+    zs = ctx.predictions().cpu().numpy()
+    f = _gpu_ctx(mpr, z, mask, sweep_mode=mpr.SWEEP_FUSED, **kw)
+    f.infer_temperature(20)
+    f.run(5)
+    zf = f.predictions().cpu().numpy()
+    m = (mask == 0).ravel()
+    rng_z = np.nanmax(z) - np.nanmin(z)
+    assert np.abs(zs - zf)[m].mean() <= 1e-6 * rng_z

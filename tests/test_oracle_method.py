@@ -88,17 +88,18 @@ def test_single_free_spin_high_temperature_limit():
 
 
 # ---------------------------------------------------------------- two free spins
-def test_two_free_spins_match_2d_quadrature():
+@pytest.mark.parametrize("q,J", [(0.5, 1.0), (0.3, 1.7)])
+def test_two_free_spins_match_2d_quadrature(q, J):
     """3x4 open grid with (1,1) and (1,2) free: joint density by 2-D quadrature;
-    E[phi1], E[phi2] and E[phi1 phi2] within 3 sigma."""
-    T, q = 0.25, 0.5
+    E[phi1], E[phi2] and E[phi1 phi2] within 3 sigma (also for q < 1/2 and J != 1)."""
+    T = 0.25
     z = np.full((3, 4), 0.5)
     z[0, 0], z[2, 3] = 0.0, 1.0
     z[1, 0], z[0, 1], z[2, 1] = 0.1, 0.3, 0.2      # fixed neighbours of (1,1)
     z[1, 3], z[0, 2], z[2, 2] = 0.8, 0.6, 0.7      # fixed neighbours of (1,2)
     mask = np.ones((3, 4), np.uint8)
     mask[1, 1] = mask[1, 2] = 0
-    o = O.Oracle(q=q, seed=4242, alpha0=0.5, n_threads=1)
+    o = O.Oracle(q=q, J=J, seed=4242, alpha0=0.5, n_threads=1)
     o.load(z, mask)
     o.set_temperature(T)
     o.burn_in(500)
@@ -108,7 +109,7 @@ def test_two_free_spins_match_2d_quadrature():
     x, w = _gauss_legendre(0.0, TWO_PI, n_sub=40, n=16)
     la = np.cos(q * (x[:, None] - a[None, :])).sum(axis=1)
     lb = np.cos(q * (x[:, None] - b[None, :])).sum(axis=1)
-    L = (la[:, None] + lb[None, :] + np.cos(q * (x[:, None] - x[None, :]))) / T
+    L = J * (la[:, None] + lb[None, :] + np.cos(q * (x[:, None] - x[None, :]))) / T
     P = w[:, None] * w[None, :] * np.exp(L - L.max())
     P /= P.sum()
     X1, X2 = np.meshgrid(x, x, indexing="ij")
