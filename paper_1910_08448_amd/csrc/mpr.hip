@@ -249,7 +249,7 @@ __global__ void k_infer_end(const GcDesc* gcs, GcCtl* ctl, const GcCtl* ictl, co
             na += A[k * kAccStride + 2];
         }
         const GcDesc g = gcs[i];
-        control_step(c, -J * fix2_value(eh, el) / (double)g.n_bonds, na, g.n_pred,
+        control_step(c, -J * fix2_value(eh, el) * g.inv_n_bonds, na, g,
                      run->trace_base + t >= run->s_half, J, acc_target, T_min, T_max, 0.0, false,
                      trace + ((int64_t)i * run->trace_cap + t) * 4);
     }
@@ -319,11 +319,11 @@ __global__ __launch_bounds__(1024) void k_control(const GcDesc* gcs, GcCtl* ctl,
         r_single = (double)(den <= 1e-30f ? 2.0f : num / den);
         e_sim = (double)es;
     } else {
-        e_sim = -J * fix2_value(e, el) / (double)g.n_bonds;
+        e_sim = -J * fix2_value(e, el) * g.inv_n_bonds;
     }
     const int64_t t = s - run->trace_base;
     double* tr = (t >= 0 && t < run->trace_cap) ? trace + ((int64_t)blockIdx.x * run->trace_cap + t) * 4 : nullptr;
-    control_step(c, e_sim, na, g.n_pred, s >= run->s_half, J, acc_target, T_min, T_max, r_single,
+    control_step(c, e_sim, na, g, s >= run->s_half, J, acc_target, T_min, T_max, r_single,
                  ESINGLE, tr);
     ctl[blockIdx.x] = c;
 }
@@ -848,6 +848,7 @@ static int setup_shapes(mpr_ctx* c, int G, const int64_t* H, const int64_t* W)
             plane += 2 * (int64_t)d.H * d.pitch;
             d.grid_site_off = c->site_off[g];
             d.n_bonds = per ? 2 * H[g] * W[g] : 2 * H[g] * W[g] - H[g] - W[g];
+            d.inv_n_bonds = d.n_bonds > 0 ? 1.0 / (double)d.n_bonds : 0.0;
             c->gcs.push_back(d);
         }
     c->rows = choose_rows(c);
@@ -1216,6 +1217,7 @@ static int load_common(mpr_ctx* c, const double* z, const uint8_t* mask)
         if (G.n_sample_bonds == 0)
             return fail(c, MPR_ENOSAMPLE, "grid %d: no bond joins two sample sites", d.grid);
         d.n_pred = G.n_pred;
+        d.inv_n_pred = G.n_pred > 0 ? 1.0 / (double)G.n_pred : 0.0;
         GcCtl& k = ctl[i];
         std::memset(&k, 0, sizeof k);
         k.alpha = c->cfg.alpha0;

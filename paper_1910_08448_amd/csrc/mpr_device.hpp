@@ -31,6 +31,8 @@ struct GcDesc {            // one (grid, chain)
     int64_t grid_site_off; // offset into packed per-grid site arrays (z, mask, zhat)
     int64_t n_pred;        // prediction sites of the grid
     int64_t n_bonds;       // nearest-neighbour bonds of the grid
+    double inv_n_pred;     // 1 / n_pred (0 without prediction sites), 1 / n_bonds: the control
+    double inv_n_bonds;    // step multiplies instead of dividing (every wave evaluates it)
 };
 
 struct Item {              // one wave's work: 60 output pairs x rows [y0, y1)
@@ -434,11 +436,11 @@ __host__ __device__ inline double fix2_value(int64_t hi, int64_t lo)
 // moved by the clamped ratio (e_smp + J) / (e_sim + J), alpha by A / A_target.  `c` holds the
 // state used by the sweep and becomes the state of the next one; tr (if not null) receives the
 // sweep's trace entry (e_sim, T, alpha, A).
-__device__ inline void control_step(GcCtl& c, double e_sim, int64_t n_acc, int64_t n_pred,
+__device__ inline void control_step(GcCtl& c, double e_sim, int64_t n_acc, const GcDesc& g,
                                     bool second_half, double J, double acc_target, double T_min,
                                     double T_max, double r_single, bool use_single, double* tr)
 {
-    const double A = n_pred > 0 ? (double)n_acc / (double)n_pred : acc_target;
+    const double A = g.n_pred > 0 ? (double)n_acc * g.inv_n_pred : acc_target;
     double r;
     if (use_single) r = r_single;
     else {
@@ -449,7 +451,7 @@ __device__ inline void control_step(GcCtl& c, double e_sim, int64_t n_acc, int64
     if (second_half) { c.T_sum += c.T; c.T_cnt += 1; }
     r = fmin(fmax(r, 0.5), 2.0);
     c.T = fmin(fmax(c.T * r, T_min), T_max);
-    c.alpha = fmin(fmax(c.alpha * A / acc_target, 1e-3), 1.0);
+    c.alpha = fmin(fmax(c.alpha * (A / acc_target), 1e-3), 1.0);
     c.e_sim = e_sim;
     c.acc_rate = A;
 }
@@ -472,53 +474,6 @@ __device__ __forceinline__ double from_right(double v)
     const long long b = __double_as_longlong(v);
     const int lo = dpp_from_right((int)(b & 0xffffffffll)), hi = dpp_from_right((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Control state used by a sweep of (grid, chain) gc.  Frozen (ctl) outside an inference or when
-// the energy is summed in single precision; during an inference either applied here (apply:
-// the control step of the previous sweep from its exact sums, by every wave alike; the lead
-// wave stores the result, the trace entry, and resets the accumulator slot after next, whose
-// copy 0 starts at econst[gc] if given) or read as stored by the kernel that applied it.
-__device__ inline GcCtl sweep_control(bool fused, bool apply, int gc, const GcDesc& g, bool lead,
-                                      int lane, const GcCtl* ctl, const RunCtl* run, GcCtl* ictl,
-                                      int64_t* gacc, const int64_t* econst, double* trace,
-                                      int n_gc, int64_t s_abs, double J, double acc_target,
-                                      double T_min, double T_max, int& acc_slot)
-{
-    acc_slot = 0;
-    if (!fused) return ctl[gc];
-    const int64_t t = s_abs - run->trace_base;
-    const bool infer = (t >= 0) & (t < run->n_infer);
-    if (!infer) return ctl[gc];
-    const int tm = (int)t;
-    acc_slot = tm % 3;
-    if (!apply || tm == 0) return ictl[(tm & 1) * n_gc + gc];
-    GcCtl c = ictl[((tm - 1) & 1) * n_gc + gc];
-    const int64_t* A = gacc + ((int64_t)((tm - 1) % 3) * n_gc + gc) * kAccPerGc;
-    int64_t eh = 0, el = 0, na = 0;
-    if (lane < kAccCopies) {
-        eh = A[lane * kAccStride];
-        el = A[lane * kAccStride + 1];
-        na = A[lane * kAccStride + 2];
-    }
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        eh += __shfl_xor(eh, off, kWave);
-        el += __shfl_xor(el, off, kWave);
-        na += __shfl_xor(na, off, kWave);
-    }
-    double* tr = (lead && lane == 0) ? trace + ((int64_t)gc * run->trace_cap + (tm - 1)) * 4 : nullptr;
-    control_step(c, -J * fix2_value(eh, el) / (double)g.n_bonds, na, g.n_pred,
-                 s_abs - 1 >= run->s_half, J, acc_target, T_min, T_max, 0.0, false, tr);
-    if (lead) {
-        if (lane == 0) ictl[(tm & 1) * n_gc + gc] = c;
-        if (lane < kAccCopies) {
-            int64_t* z = gacc + ((int64_t)((tm + 1) % 3) * n_gc + gc) * kAccPerGc + lane * kAccStride;
-            z[0] = (econst && lane == 0) ? econst[2 * gc] : 0;
-            z[1] = (econst && lane == 0) ? econst[2 * gc + 1] : 0;
-            z[2] = 0;
-        }
-    }
-    return c;
 }
 
 // XCD-aware block order: the dispatcher hands block b to XCD b % 8, each XCD with its own L2, so
@@ -555,6 +510,52 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t x)
     const int b = (int)((x >> 21) & 0x1FFFFF);
     const int a = (int)(x >> 42);
     return ((int64_t)wave_sum_i32(a) << 42) + ((int64_t)wave_sum_i32(b) << 21) + (int64_t)wave_sum_i32(c);
+}
+
+// Control state used by a sweep of (grid, chain) gc.  Frozen (ctl) outside an inference or when
+// the energy is summed in single precision; during an inference either applied here (apply:
+// the control step of the previous sweep from its exact sums, by every wave alike; the lead
+// wave stores the result, the trace entry, and resets the accumulator slot after next, whose
+// copy 0 starts at econst[gc] if given) or read as stored by the kernel that applied it.
+__device__ inline GcCtl sweep_control(bool fused, bool apply, int gc, const GcDesc& g, bool lead,
+                                      int lane, const GcCtl* ctl, const RunCtl* run, GcCtl* ictl,
+                                      int64_t* gacc, const int64_t* econst, double* trace,
+                                      int n_gc, int64_t s_abs, double J, double acc_target,
+                                      double T_min, double T_max, int& acc_slot)
+{
+    acc_slot = 0;
+    if (!fused) return ctl[gc];
+    const int64_t t = s_abs - run->trace_base;
+    const bool infer = (t >= 0) & (t < run->n_infer);
+    if (!infer) return ctl[gc];
+    const int tm = (int)t;
+    acc_slot = tm % 3;
+    if (!apply || tm == 0) return ictl[(tm & 1) * n_gc + gc];
+    GcCtl c = ictl[((tm - 1) & 1) * n_gc + gc];
+    const int64_t* A = gacc + ((int64_t)((tm - 1) % 3) * n_gc + gc) * kAccPerGc;
+    int64_t eh = 0, el = 0, na = 0;
+    if (lane < kAccCopies) {
+        eh = A[lane * kAccStride];
+        el = A[lane * kAccStride + 1];
+        na = A[lane * kAccStride + 2];
+    }
+    // 16 nonzero lanes: each 21-bit limb total stays below 2^26 for any int64 word
+    eh = wave_sum_i64(eh);
+    el = wave_sum_i64(el);
+    na = wave_sum_i64(na);
+    double* tr = (lead && lane == 0) ? trace + ((int64_t)gc * run->trace_cap + (tm - 1)) * 4 : nullptr;
+    control_step(c, -J * fix2_value(eh, el) * g.inv_n_bonds, na, g,
+                 s_abs - 1 >= run->s_half, J, acc_target, T_min, T_max, 0.0, false, tr);
+    if (lead) {
+        if (lane == 0) ictl[(tm & 1) * n_gc + gc] = c;
+        if (lane < kAccCopies) {
+            int64_t* z = gacc + ((int64_t)((tm + 1) % 3) * n_gc + gc) * kAccPerGc + lane * kAccStride;
+            z[0] = (econst && lane == 0) ? econst[2 * gc] : 0;
+            z[1] = (econst && lane == 0) ? econst[2 * gc + 1] : 0;
+            z[2] = 0;
+        }
+    }
+    return c;
 }
 
 // per-row data of one lane: (cos, sin) of both pair members, zero where the site is absent
