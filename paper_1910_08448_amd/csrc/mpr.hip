@@ -659,6 +659,7 @@ struct mpr_ctx {
     int32_t* d_lead[2] = {nullptr, nullptr};
     int64_t waves_cap[2] = {0, 0};
     int32_t n_waves[2] = {0, 0};
+    int64_t list_base0[2] = {0, 0};                          // grid 0's list starts
     int64_t* d_econst = nullptr;                             // [n_gc][2]
     int32_t* d_rowcnt = nullptr;                             // scratch of the list build
     int64_t rowcnt_cap = 0, lead_cap[2] = {0, 0}, econst_cap = 0;
@@ -1027,6 +1028,8 @@ static int build_lists(mpr_ctx* c)
             return fail(c, MPR_EINVAL, "too many prediction sites for the compacted path");
     }
     if (entries > (int64_t)INT32_MAX) return fail(c, MPR_EINVAL, "too many prediction sites for the compacted path");
+    c->list_base0[0] = meta[G];
+    c->list_base0[1] = meta[G + 1];
     rc = ensure_buffer(c, (void**)&c->d_sites, &c->sites_cap, entries * 4);
     if (rc) return rc;
     HIPCHK(c, hipMemsetAsync(c->d_sites, 0xff, entries * 4, c->stream));
@@ -1317,6 +1320,8 @@ static void enqueue_sparse(mpr_ctx* c, int flags, int sweep_off, const RunCtl* r
         a.sweep_off = sweep_off;
         a.key0 = (uint32_t)(c->cfg.seed & 0xffffffffu);
         a.key1 = (uint32_t)(c->cfg.seed >> 32);
+        a.single = c->gcs.size() == 1;
+        a.single_base = c->list_base0[col];
         const unsigned blocks = (unsigned)((c->n_waves[col] + kWavesPerBlock - 1) / kWavesPerBlock);
         hipLaunchKernelGGL(sparse_fn(c, flags, col), dim3(blocks), dim3(kWave * kWavesPerBlock), 0,
                            c->stream, a);

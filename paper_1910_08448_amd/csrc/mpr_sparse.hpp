@@ -35,6 +35,10 @@ struct SparseArgs {
     double acc_target, T_min, T_max, q, J;
     int32_t n_gc, n_waves, sweep_off;
     uint32_t key0, key1;
+    // one grid and one chain: the wave's entries follow from its index, so the site loads wait
+    // for no table read (the (grid, chain) record is read alongside)
+    int32_t single;
+    int64_t single_base;       // first entry of this colour's list
 };
 
 template <class St>
@@ -79,9 +83,17 @@ __global__ __launch_bounds__(256) void k_sparse(SparseArgs a)
     const int lblock = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int wid = __builtin_amdgcn_readfirstlane(lblock * kWavesPerBlock + (int)(threadIdx.x >> 6));
     if (wid >= a.n_waves) return;                 // whole waves leave together
-    const int2 wv = a.waves[wid];
-    const int gc = __builtin_amdgcn_readfirstlane(wv.x);
-    const uint32_t ent = a.sites[(int64_t)wv.y + lane];
+    int gc;
+    int64_t base;
+    if (a.single) {
+        gc = 0;
+        base = a.single_base + (int64_t)wid * kWave;
+    } else {
+        const int2 wv = a.waves[wid];
+        gc = __builtin_amdgcn_readfirstlane(wv.x);
+        base = wv.y;
+    }
+    const uint32_t ent = a.sites[base + lane];
     const GcDesc g = a.gcs[gc];
     const int64_t s_abs = a.run->base_sweep + a.sweep_off;
     const uint32_t sweep = (uint32_t)s_abs;
@@ -181,7 +193,7 @@ __global__ __launch_bounds__(256) void k_sparse(SparseArgs a)
         // a full block of one (grid, chain) adds once (block-uniform test)
         const int b0 = lblock * kWavesPerBlock;
         const bool whole = (b0 + kWavesPerBlock <= a.n_waves) &&
-                           (a.waves[b0].x == a.waves[b0 + kWavesPerBlock - 1].x);
+                           (a.single || a.waves[b0].x == a.waves[b0 + kWavesPerBlock - 1].x);
         if (whole) {
             __shared__ int64_t red[kWavesPerBlock][3];
             const int w = (int)(threadIdx.x >> 6);
