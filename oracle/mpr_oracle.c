@@ -368,11 +368,14 @@ int orc_load(orc_ctx* c, int64_t H, int64_t W, const double* z, const uint8_t* m
 
 static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-int orc_infer_temperature(orc_ctx* c, int32_t n_equil, double* T_out)
+/* n conditional sweeps per chain with the control and the per-sweep trace.  fixed = 0: the
+ * temperature follows the energy matching from T_0 and the window the acceptance; FIX_T: the
+ * temperature stays at each chain's current value; FIX_T | FIX_ALPHA: the window stays too.
+ * T_hat = mean of the temperatures used in sweeps floor(n/2) .. n-1 (with a fixed T, that T
+ * itself). */
+enum { FIX_T = 1, FIX_ALPHA = 2 };
+static int sweep_loop(orc_ctx* c, int32_t n_equil, int fixed, double* T_out)
 {
-    if (!c) return ORC_EINVAL;
-    if (c->phase < PH_LOADED) return ORC_ESTATE;
-    if (n_equil < 0) return ORC_EINVAL;
     const orc_config* g = &c->cfg;
     int C = g->n_chains;
     free(c->trace);
@@ -383,7 +386,7 @@ int orc_infer_temperature(orc_ctx* c, int32_t n_equil, double* T_out)
     double T0 = clampd(4.0 * (c->e_smp + g->J), g->T_min, g->T_max);
     for (int ch = 0; ch < C; ++ch) {
         double* p = c->phi + (size_t)ch * c->n;
-        double T = T0, a = c->alpha[ch], Tsum = 0.0;
+        double T = (fixed & FIX_T) ? c->T[ch] : T0, a = c->alpha[ch], Tsum = 0.0;
         int64_t Tcnt = 0;
         for (int32_t s = 0; s < n_equil; ++s) {
             int64_t acc = orc_sweep(c->H, c->W, p, c->mask, g->boundary, g->q, g->J, T, a,
@@ -396,23 +399,125 @@ int orc_infer_temperature(orc_ctx* c, int32_t n_equil, double* T_out)
             double* tr = c->trace + ((size_t)ch * n_equil + s) * 4;
             tr[0] = e_sim; tr[1] = T; tr[2] = a; tr[3] = A;
             if (s >= n_equil / 2) { Tsum += T; ++Tcnt; }
-            /* temperature control: multiplicative energy matching */
-            double num = c->e_smp + g->J, den = e_sim + g->J;
-            double r = den <= 1e-300 ? 2.0 : num / den;
-            r = clampd(r, 0.5, 2.0);
-            T = clampd(T * r, g->T_min, g->T_max);
+            if (!(fixed & FIX_T)) {
+                /* temperature control: multiplicative energy matching */
+                double num = c->e_smp + g->J, den = e_sim + g->J;
+                double r = den <= 1e-300 ? 2.0 : num / den;
+                r = clampd(r, 0.5, 2.0);
+                T = clampd(T * r, g->T_min, g->T_max);
+            }
             /* Metropolis window control */
-            a = clampd(a * A / g->acc_target, 1e-3, 1.0);
+            if (!(fixed & FIX_ALPHA)) a = clampd(a * A / g->acc_target, 1e-3, 1.0);
             c->e_sim[ch] = e_sim;
             c->acc_rate[ch] = A;
         }
-        c->T[ch] = Tcnt > 0 ? Tsum / (double)Tcnt : T0;
+        if (!(fixed & FIX_T)) c->T[ch] = Tcnt > 0 ? Tsum / (double)Tcnt : T0;
         c->alpha[ch] = a;
         if (T_out) T_out[ch] = c->T[ch];
     }
     c->trace_len = n_equil;
     c->next_sweep += n_equil;
     c->phase = PH_TEMPERED;
+    return ORC_OK;
+}
+
+int orc_infer_temperature(orc_ctx* c, int32_t n_equil, double* T_out)
+{
+    if (!c) return ORC_EINVAL;
+    if (c->phase < PH_LOADED) return ORC_ESTATE;
+    if (n_equil < 0) return ORC_EINVAL;
+    return sweep_loop(c, n_equil, 0, T_out);
+}
+
+int orc_equilibrate(orc_ctx* c, int32_t n, double* T_out)
+{
+    if (!c) return ORC_EINVAL;
+    if (c->phase < PH_TEMPERED) return ORC_ESTATE;
+    if (n < 0) return ORC_EINVAL;
+    return sweep_loop(c, n, FIX_T, T_out);
+}
+
+/* ------------------------------------------------------------------ energy-temperature curve */
+int orc_energy_curve(const orc_config* cfg, int64_t side, int32_t n_T, const double* T,
+                     int32_t n_burn, int32_t n_meas, double* e_out, double* trace_out)
+{
+    if (!cfg || !T || !e_out || n_T < 1 || n_burn < 0 || n_meas < 1) return ORC_EINVAL;
+    if (side < 2 || (side & 1)) return ORC_EBIPARTITE;
+    for (int32_t i = 0; i < n_T; ++i)
+        if (!(T[i] > 0.0) || !isfinite(T[i])) return ORC_EINVAL;
+    orc_config g = *cfg;
+    g.boundary = ORC_PERIODIC;
+    g.n_chains = n_T;
+    orc_ctx* c = NULL;
+    int rc = orc_create(&g, &c);
+    if (rc) return rc;
+    int64_t n = side * side;
+    c->H = side; c->W = side; c->n = n;
+    c->z = (double*)calloc((size_t)n, sizeof(double));
+    c->mask = (uint8_t*)calloc((size_t)n, 1);               /* no data: every site free */
+    c->phi = (double*)calloc((size_t)n * n_T, sizeof(double));
+    c->acc = (double*)calloc((size_t)n * n_T, sizeof(double));
+    c->T = (double*)calloc((size_t)n_T, sizeof(double));
+    c->alpha = (double*)calloc((size_t)n_T, sizeof(double));
+    c->e_sim = (double*)calloc((size_t)n_T, sizeof(double));
+    c->acc_rate = (double*)calloc((size_t)n_T, sizeof(double));
+    if (!c->z || !c->mask || !c->phi || !c->acc || !c->T || !c->alpha || !c->e_sim ||
+        !c->acc_rate) { orc_destroy(c); return ORC_ENOMEM; }
+    c->n_pred = n;
+    c->n_bonds = 2 * n;
+    for (int32_t i = 0; i < n_T; ++i) {
+        orc_init_chain(side, side, c->phi + (size_t)i * n, c->mask, g.seed, chain_word(c, i));
+        c->alpha[i] = g.alpha0;
+        c->T[i] = T[i];
+    }
+    c->phase = PH_TEMPERED;
+    /* burn-in with the window control, then measurement at a fixed window: a window that
+     * follows the chain's own acceptance makes the transition kernel depend on its past */
+    const int32_t total = n_burn + n_meas;
+    rc = sweep_loop(c, n_burn, FIX_T, NULL);
+    if (!rc && trace_out)
+        for (int32_t i = 0; i < n_T; ++i)
+            memcpy(trace_out + (size_t)i * total * 4, c->trace + (size_t)i * n_burn * 4,
+                   (size_t)n_burn * 4 * sizeof(double));
+    if (!rc) rc = sweep_loop(c, n_meas, FIX_T | FIX_ALPHA, NULL);
+    if (rc) { orc_destroy(c); return rc; }
+    for (int32_t i = 0; i < n_T; ++i) {
+        double s = 0.0;
+        for (int32_t k = 0; k < n_meas; ++k) s += c->trace[((size_t)i * n_meas + k) * 4];
+        e_out[i] = s / (double)n_meas;
+        if (trace_out)
+            memcpy(trace_out + ((size_t)i * total + n_burn) * 4, c->trace + (size_t)i * n_meas * 4,
+                   (size_t)n_meas * 4 * sizeof(double));
+    }
+    orc_destroy(c);
+    return ORC_OK;
+}
+
+double orc_curve_temperature(int32_t n_T, const double* T, const double* e, double e_target)
+{
+    if (n_T < 2 || e_target <= e[0]) return T[0];
+    for (int32_t i = 0; i + 1 < n_T; ++i)
+        if (e_target <= e[i + 1]) {
+            const double de = e[i + 1] - e[i];
+            if (!(de > 0.0)) return T[i];
+            return T[i] + (T[i + 1] - T[i]) * ((e_target - e[i]) / de);
+        }
+    return T[n_T - 1];
+}
+
+int orc_set_temperature_curve(orc_ctx* c, int32_t n_T, const double* T, const double* e,
+                              double* T_out)
+{
+    if (!c || !T || !e || n_T < 1) return ORC_EINVAL;
+    if (c->phase < PH_LOADED) return ORC_ESTATE;
+    for (int32_t i = 0; i < n_T; ++i)
+        if (!(T[i] > 0.0) || (i > 0 && !(T[i] > T[i - 1]))) return ORC_EINVAL;
+    const double Th = orc_curve_temperature(n_T, T, e, c->e_smp);
+    for (int ch = 0; ch < c->cfg.n_chains; ++ch) {
+        c->T[ch] = Th;
+        if (T_out) T_out[ch] = Th;
+    }
+    if (c->phase < PH_TEMPERED) c->phase = PH_TEMPERED;
     return ORC_OK;
 }
 

@@ -115,6 +115,24 @@ int  orc_set_state(orc_ctx* ctx, const double* phi, const double* acc, const dou
 int  orc_debug_sweep(orc_ctx* ctx, int32_t sweep, uint8_t* decisions);
 /* n sweeps at the current (fixed) T and alpha, without averaging */
 int  orc_burn_in(orc_ctx* ctx, int32_t n);
+/* n sweeps at each chain's current (fixed) T with the window control and the trace of the
+ * inference; T_hat = that T */
+int  orc_equilibrate(orc_ctx* ctx, int32_t n, double* T_out);
+
+/* ---- alternative temperature reading: invert the model's energy-temperature curve ----
+ * Unconditional mean bond energy of Eq. (2) (no data) on a periodic side x side lattice at
+ * each T[i]: chain i (counter word grid_id * n_T + i) starts from the (tag 1, sweep 0) uniform
+ * state and runs n_burn sweeps at fixed T[i] with the window control, then n_meas sweeps with
+ * the window fixed; e_out[i] = mean e over the n_meas sweeps; trace_out (may be NULL) gets
+ * [n_T][n_burn + n_meas][4]. */
+int  orc_energy_curve(const orc_config* cfg, int64_t side, int32_t n_T, const double* T,
+                      int32_t n_burn, int32_t n_meas, double* e_out, double* trace_out);
+/* T with e(T) = e_target, linear between the bracketing points of a curve sampled at
+ * increasing T (first bracket from the low end), clamped to the end points */
+double orc_curve_temperature(int32_t n_T, const double* T, const double* e, double e_target);
+/* every chain's T <- the curve's temperature at the loaded data's sample energy */
+int  orc_set_temperature_curve(orc_ctx* ctx, int32_t n_T, const double* T, const double* e,
+                               double* T_out);
 /* n sweeps of chain 0 at its current T and alpha; phi of the listed sites after each sweep
  * goes to out[n][n_sites] */
 int  orc_run_record(orc_ctx* ctx, int32_t n, int32_t n_sites, const int64_t* sites, double* out);

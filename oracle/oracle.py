@@ -90,6 +90,10 @@ def lib():
             "orc_debug_sweep": (ctypes.c_int, [_vp, _i32, _vp]),
             "orc_burn_in": (ctypes.c_int, [_vp, _i32]),
             "orc_run_record": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp]),
+            "orc_equilibrate": (ctypes.c_int, [_vp, _i32, _vp]),
+            "orc_energy_curve": (ctypes.c_int, [_vp, _i64, _i32, _vp, _i32, _i32, _vp, _vp]),
+            "orc_curve_temperature": (_d, [_i32, _vp, _vp, _d]),
+            "orc_set_temperature_curve": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -278,12 +282,43 @@ class Oracle:
     def burn_in(self, n):
         _chk(lib().orc_burn_in(self.h, n), "orc_burn_in")
 
+    def equilibrate(self, n):
+        T = np.zeros(self.cfg.n_chains)
+        _chk(lib().orc_equilibrate(self.h, n, _ptr(T)), "orc_equilibrate")
+        return T
+
+    def set_temperature_curve(self, T, e):
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        e = np.ascontiguousarray(e, dtype=np.float64)
+        out = np.zeros(self.cfg.n_chains)
+        _chk(lib().orc_set_temperature_curve(self.h, T.size, _ptr(T), _ptr(e), _ptr(out)),
+             "orc_set_temperature_curve")
+        return out
+
     def run_record(self, n, sites):
         sites = np.ascontiguousarray(np.atleast_1d(sites), dtype=np.int64)
         out = np.zeros((n, sites.size))
         _chk(lib().orc_run_record(self.h, n, sites.size, _ptr(sites), _ptr(out)),
              "orc_run_record")
         return out
+
+
+def energy_curve(side, T, n_burn, n_meas, with_trace=False, **kw):
+    """Unconditional mean bond energy e(T) on a periodic side x side lattice (see the C header);
+    returns e (and the per-sweep trace [n_T][n_burn + n_meas][4] if with_trace)."""
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    cfg = config(**kw)
+    e = np.zeros(T.size)
+    tr = np.zeros((T.size, n_burn + n_meas, 4)) if with_trace else None
+    _chk(lib().orc_energy_curve(ctypes.byref(cfg), side, T.size, _ptr(T), n_burn, n_meas,
+                                _ptr(e), _ptr(tr)), "orc_energy_curve")
+    return (e, tr) if with_trace else e
+
+
+def curve_temperature(T, e, e_target):
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    return lib().orc_curve_temperature(T.size, _ptr(T), _ptr(e), e_target)
 
 
 def predict(z, mask, n_equil, n_avg, **kw):
