@@ -142,6 +142,39 @@ int mpr_infer_temperature(mpr_ctx* ctx, int32_t n_equil, double* T_host);
 /* Use temperature T for every chain instead of inferring it. */
 int mpr_set_temperature(mpr_ctx* ctx, double T);
 
+/* n hybrid sweeps at each chain's current temperature (kept fixed) with the Metropolis window
+ * control and the per-sweep trace of mpr_infer_temperature (Sec. 2: conditional simulation in
+ * equilibrium at the inferred T).  T_host (may be NULL) receives the unchanged temperatures.
+ * ESTATE before a temperature is set or inferred; EINVAL for n < 0. */
+int mpr_equilibrate(mpr_ctx* ctx, int32_t n, double* T_host);
+
+/* Second reading of the temperature inference of Sec. 2: match the sample energy to the
+ * unconditional (data-free) model instead of the conditional simulation.
+ *
+ * mpr_energy_curve: mean bond energy e(T) = -(J/|B|) sum over all bonds of cos[q(phi_i-phi_j)]
+ * (Eq. (2)) of the model with no data on a periodic side x side lattice, at each of the n_T
+ * temperatures T_host[i] (host array, finite and > 0).  Chain i (Philox chain word
+ * grid_offset * n_T + i, every site drawn uniformly at sweep 0) runs n_burn hybrid sweeps at
+ * fixed T_host[i] with the window control of cfg, then n_meas sweeps with the window fixed (an
+ * adapting window makes the kernel depend on the chain's past, which biases the average);
+ * e_host[i] (host) = mean of e over the n_meas sweeps; trace_host (host, may be NULL) receives
+ * [n_T][n_burn + n_meas][4] = (e, T, alpha, acceptance) of every sweep.  Uses cfg's q, J, precision, seed, alpha0, acc_target and
+ * grid_offset; the boundary is periodic and the sweep path the row-window one whatever cfg
+ * says.  side must be even, >= 4 and divisible by 4 (periodic lattices; EINVAL / EBIPARTITE
+ * otherwise); n_burn >= 0, n_meas >= 1.  Allocates and frees its own device memory, runs on
+ * `hip_stream` (a hipStream_t, NULL = default) and synchronises before returning.
+ *
+ * mpr_set_temperature_curve: every chain's T <- the curve's temperature at its grid's sample
+ * energy e_smp: linear between the first pair of points (from the low-T end) whose energies
+ * bracket e_smp, T_host[0] below the curve, T_host[n_T-1] above it.  T_host ascending, n_T >= 1,
+ * finite values (EINVAL otherwise).  T_out (host, may be NULL) receives the temperatures
+ * [n_grids * n_chains].  Needs loaded data (ESTATE). */
+int mpr_energy_curve(const mpr_config* cfg, void* hip_stream, int32_t side, int32_t n_T,
+                     const double* T_host, int32_t n_burn, int32_t n_meas, double* e_host,
+                     double* trace_host);
+int mpr_set_temperature_curve(mpr_ctx* ctx, int32_t n_T, const double* T_host,
+                              const double* e_host, double* T_out);
+
 /* n sweeps at the current temperatures and windows, without averaging (no control). */
 int mpr_burn_in(mpr_ctx* ctx, int32_t n);
 

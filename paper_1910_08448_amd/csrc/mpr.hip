@@ -204,12 +204,14 @@ __global__ __launch_bounds__(256) void k_copy_z(const GridInfo* gi, const double
 // ------------------------------------------------------------------ control kernels
 __global__ void k_infer_begin(GcCtl* ctl, GcCtl* ictl, int64_t* gacc, const int64_t* econst,
                               int n_gc, double J, double T_min, double T_max, RunCtl* run,
-                              int64_t s_half, int64_t trace_base, int64_t trace_cap, int64_t n_infer)
+                              int64_t s_half, int64_t trace_base, int64_t trace_cap, int64_t n_infer,
+                              int fixed)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) {
         run->s_half = s_half; run->trace_base = trace_base; run->trace_cap = trace_cap;
         run->n_infer = n_infer;
+        run->fixed = fixed;
     }
     if (i < 3 * n_gc * kAccCopies) {                // thread i clears copy i of all slots
         int64_t* z = gacc + (int64_t)i * kAccStride;
@@ -221,7 +223,8 @@ __global__ void k_infer_begin(GcCtl* ctl, GcCtl* ictl, int64_t* gacc, const int6
     }
     if (i >= n_gc) return;
     GcCtl& c = ctl[i];
-    const double T0 = fmin(fmax(4.0 * (c.e_smp + J), T_min), T_max);
+    // the matching starts from T_0 = clamp(4 (e_smp + J)); an equilibration keeps its T
+    const double T0 = (fixed & kFixT) ? c.T : fmin(fmax(4.0 * (c.e_smp + J), T_min), T_max);
     c.T0 = T0;
     c.T = T0;
     c.T_sum = 0.0;
@@ -251,10 +254,31 @@ __global__ void k_infer_end(const GcDesc* gcs, GcCtl* ctl, const GcCtl* ictl, co
         const GcDesc g = gcs[i];
         control_step(c, -J * fix2_value(eh, el) * g.inv_n_bonds, na, g,
                      run->trace_base + t >= run->s_half, J, acc_target, T_min, T_max, 0.0, false,
-                     trace + ((int64_t)i * run->trace_cap + t) * 4);
+                     trace + ((int64_t)i * run->trace_cap + t) * 4, run->fixed);
     }
-    c.T = c.T_cnt > 0 ? c.T_sum / (double)c.T_cnt : c.T0;
+    if (!(run->fixed & kFixT)) c.T = c.T_cnt > 0 ? c.T_sum / (double)c.T_cnt : c.T0;
     ctl[i] = c;
+}
+
+// temperature from a sampled energy-temperature curve of the unconditional model (T ascending):
+// the T at which the curve reaches the (grid, chain)'s sample energy, linear between the first
+// bracketing pair of points from the low end, clamped to the end points
+__global__ void k_curve_temperature(GcCtl* ctl, int n_gc, const double* T, const double* e, int n_T)
+{
+#pragma clang fp contract(off)
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_gc) return;
+    const double et = ctl[i].e_smp;
+    double r = T[n_T - 1];
+    if (n_T < 2 || et <= e[0]) r = T[0];
+    else
+        for (int k = 0; k + 1 < n_T; ++k)
+            if (et <= e[k + 1]) {
+                const double de = e[k + 1] - e[k];
+                r = de > 0.0 ? T[k] + (T[k + 1] - T[k]) * ((et - e[k]) / de) : T[k];
+                break;
+            }
+    ctl[i].T = r;
 }
 
 __global__ void k_advance(RunCtl* run, int64_t n) { run->base_sweep += n; }
@@ -324,7 +348,7 @@ __global__ __launch_bounds__(1024) void k_control(const GcDesc* gcs, GcCtl* ctl,
     const int64_t t = s - run->trace_base;
     double* tr = (t >= 0 && t < run->trace_cap) ? trace + ((int64_t)blockIdx.x * run->trace_cap + t) * 4 : nullptr;
     control_step(c, e_sim, na, g, s >= run->s_half, J, acc_target, T_min, T_max, r_single,
-                 ESINGLE, tr);
+                 ESINGLE, tr, run->fixed);
     ctl[blockIdx.x] = c;
 }
 
@@ -1174,7 +1198,8 @@ static int usable(mpr_ctx* c)
 
 static int autotune(mpr_ctx* c, int n, int* best_out);
 
-static int load_common(mpr_ctx* c, const double* z, const uint8_t* mask)
+// free_only: a lattice with no data at all (the unconditional model of the energy curve)
+static int load_common(mpr_ctx* c, const double* z, const uint8_t* mask, bool free_only = false)
 {
     int rc = alloc_device(c);
     if (rc) return rc;
@@ -1191,7 +1216,7 @@ static int load_common(mpr_ctx* c, const double* z, const uint8_t* mask)
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(c->gi.data(), c->d_gi, c->G * sizeof(GridInfo), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int g = 0; g < c->G; ++g) {
+    for (int g = 0; g < c->G && !free_only; ++g) {
         GridInfo& G = c->gi[g];
         if (G.flags & 1) return fail(c, MPR_EINVAL, "grid %d: mask values must be 0 or 1", g);
         if (G.flags & 2) return fail(c, MPR_EINVAL, "grid %d: non-finite value at a sample site", g);
@@ -1217,14 +1242,14 @@ static int load_common(mpr_ctx* c, const double* z, const uint8_t* mask)
     for (size_t i = 0; i < c->gcs.size(); ++i) {
         GcDesc& d = c->gcs[i];
         const GridInfo& G = c->gi[d.grid];
-        if (G.n_sample_bonds == 0)
+        if (G.n_sample_bonds == 0 && !free_only)
             return fail(c, MPR_ENOSAMPLE, "grid %d: no bond joins two sample sites", d.grid);
         d.n_pred = G.n_pred;
         d.inv_n_pred = G.n_pred > 0 ? 1.0 / (double)G.n_pred : 0.0;
         GcCtl& k = ctl[i];
         std::memset(&k, 0, sizeof k);
         k.alpha = c->cfg.alpha0;
-        k.e_smp = -c->cfg.J * fix2_value(G.e_hi, G.e_lo) / (double)G.n_sample_bonds;
+        k.e_smp = free_only ? 0.0 : -c->cfg.J * fix2_value(G.e_hi, G.e_lo) / (double)G.n_sample_bonds;
     }
     HIPCHK(c, h2d(c, c->d_gcs, c->gcs.data(), c->gcs.size() * sizeof(GcDesc)));
     HIPCHK(c, h2d(c, c->d_ctl, ctl.data(), ctl.size() * sizeof(GcCtl)));
@@ -1418,12 +1443,11 @@ static int run_sweeps(mpr_ctx* c, int mode, int n)
     return MPR_OK;
 }
 
-int mpr_infer_temperature(mpr_ctx* c, int32_t n_equil, double* T_host)
+// n inference sweeps: energy matching from T_0 (fixed = 0), or equilibration at each chain's T
+// (kFixT), also with a fixed window (kFixT | kFixAlpha)
+static int infer_common(mpr_ctx* c, int32_t n_equil, int fixed, double* T_host)
 {
-    int rc = usable(c);
-    if (rc) return rc;
-    if (c->phase < PH_LOADED) return fail(c, MPR_ESTATE, "no data loaded");
-    if (n_equil < 0) return fail(c, MPR_EINVAL, "n_equil < 0");
+    int rc = MPR_OK;
     const int n_gc = (int)c->gcs.size();
     if (n_equil > c->trace_cap) {
         if (c->d_trace) (void)hipFree(c->d_trace);
@@ -1437,7 +1461,7 @@ int mpr_infer_temperature(mpr_ctx* c, int32_t n_equil, double* T_host)
                        c->d_ictl, c->d_gacc, c->sparse ? c->d_econst : nullptr, n_gc, c->cfg.J,
                        c->cfg.T_min, c->cfg.T_max, c->d_run,
                        (int64_t)(c->next_sweep + n_equil / 2), (int64_t)c->next_sweep,
-                       (int64_t)c->trace_cap, (int64_t)n_equil);
+                       (int64_t)c->trace_cap, (int64_t)n_equil, fixed);
     rc = run_sweeps(c, MODE_EQUIL, n_equil);
     if (rc) return rc;
     hipLaunchKernelGGL(k_infer_end, dim3((n_gc + 255) / 256), dim3(256), 0, c->stream, c->d_gcs,
@@ -1453,6 +1477,122 @@ int mpr_infer_temperature(mpr_ctx* c, int32_t n_equil, double* T_host)
         for (int i = 0; i < n_gc; ++i) T_host[i] = ctl[i].T;
     }
     return MPR_OK;
+}
+
+int mpr_infer_temperature(mpr_ctx* c, int32_t n_equil, double* T_host)
+{
+    int rc = usable(c);
+    if (rc) return rc;
+    if (c->phase < PH_LOADED) return fail(c, MPR_ESTATE, "no data loaded");
+    if (n_equil < 0) return fail(c, MPR_EINVAL, "n_equil < 0");
+    return infer_common(c, n_equil, 0, T_host);
+}
+
+int mpr_equilibrate(mpr_ctx* c, int32_t n, double* T_host)
+{
+    int rc = usable(c);
+    if (rc) return rc;
+    if (c->phase < PH_TEMPERED) return fail(c, MPR_ESTATE, "no temperature: infer or set it first");
+    if (n < 0) return fail(c, MPR_EINVAL, "n < 0");
+    return infer_common(c, n, kFixT, T_host);
+}
+
+int mpr_set_temperature_curve(mpr_ctx* c, int32_t n_T, const double* T_host, const double* e_host,
+                              double* T_out)
+{
+    int rc = usable(c);
+    if (rc) return rc;
+    if (c->phase < PH_LOADED) return fail(c, MPR_ESTATE, "no data loaded");
+    if (n_T < 1 || !T_host || !e_host) return fail(c, MPR_EINVAL, "bad curve arguments");
+    for (int i = 0; i < n_T; ++i)
+        if (!(T_host[i] > 0.0) || !std::isfinite(T_host[i]) || !std::isfinite(e_host[i]) ||
+            (i > 0 && !(T_host[i] > T_host[i - 1])))
+            return fail(c, MPR_EINVAL, "curve temperatures must be finite, positive and increasing");
+    double* d_tab = nullptr;
+    HIPCHK(c, hipMalloc(&d_tab, 2 * (size_t)n_T * sizeof(double)));
+    hipError_t e1 = h2d(c, d_tab, T_host, n_T * sizeof(double));
+    hipError_t e2 = e1 == hipSuccess ? h2d(c, d_tab + n_T, e_host, n_T * sizeof(double)) : e1;
+    if (e2 == hipSuccess) {
+        const int n_gc = (int)c->gcs.size();
+        hipLaunchKernelGGL(k_curve_temperature, dim3((n_gc + 255) / 256), dim3(256), 0, c->stream,
+                           c->d_ctl, n_gc, d_tab, d_tab + n_T, n_T);
+        e2 = hipGetLastError();
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
+    }
+    (void)hipFree(d_tab);
+    HIPCHK(c, e2);
+    c->phase = std::max(c->phase, (int)PH_TEMPERED);
+    if (T_out) {
+        std::vector<GcCtl> ctl(c->gcs.size());
+        HIPCHK(c, hipMemcpyAsync(ctl.data(), c->d_ctl, ctl.size() * sizeof(GcCtl), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (size_t i = 0; i < ctl.size(); ++i) T_out[i] = ctl[i].T;
+    }
+    return MPR_OK;
+}
+
+int mpr_energy_curve(const mpr_config* cfg, void* hip_stream, int32_t side, int32_t n_T,
+                     const double* T_host, int32_t n_burn, int32_t n_meas, double* e_host,
+                     double* trace_host)
+{
+    if (!cfg || !T_host || !e_host || n_T < 1 || n_burn < 0 || n_meas < 1) return MPR_EINVAL;
+    if (n_burn > INT32_MAX - n_meas) return MPR_EINVAL;
+    for (int i = 0; i < n_T; ++i)
+        if (!(T_host[i] > 0.0) || !std::isfinite(T_host[i])) return MPR_EINVAL;
+    mpr_config k = *cfg;
+    k.boundary = MPR_PERIODIC;
+    k.n_chains = n_T;
+    k.sweep_mode = MPR_SWEEP_FUSED;
+    if (k.tile_rows < 0) k.tile_rows = 0;
+    mpr_ctx* c = nullptr;
+    int rc = mpr_create(&k, hip_stream, &c);
+    if (rc) return rc;
+    const int64_t H = side, W = side;
+    rc = setup_shapes(c, 1, &H, &W);
+    // no data: a zero field and an all-zero mask, every site free
+    double* d_z = nullptr;
+    uint8_t* d_m = nullptr;
+    if (!rc && (hipMalloc(&d_z, (size_t)H * W * sizeof(double)) != hipSuccess ||
+                hipMalloc(&d_m, (size_t)H * W) != hipSuccess ||
+                hipMemsetAsync(d_z, 0, (size_t)H * W * sizeof(double), c->stream) != hipSuccess ||
+                hipMemsetAsync(d_m, 0, (size_t)H * W, c->stream) != hipSuccess))
+        rc = MPR_ENOMEM;
+    if (!rc) rc = load_common(c, d_z, d_m, true);
+    if (!rc) {
+        std::vector<GcCtl> ctl(n_T);
+        if (hipMemcpyAsync(ctl.data(), c->d_ctl, n_T * sizeof(GcCtl), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            rc = MPR_EHIP;
+        for (int i = 0; i < n_T && !rc; ++i) ctl[i].T = T_host[i];
+        if (!rc && h2d(c, c->d_ctl, ctl.data(), n_T * sizeof(GcCtl)) != hipSuccess) rc = MPR_EHIP;
+    }
+    // burn-in with the window control, then measurement sweeps with the window fixed
+    const int32_t total = n_burn + n_meas;
+    std::vector<double> tr((size_t)std::max(n_burn, n_meas) * 4);
+    for (int part = 0; part < 2 && !rc; ++part) {
+        const int32_t n = part ? n_meas : n_burn;
+        if (n == 0) continue;
+        c->phase = PH_TEMPERED;
+        rc = infer_common(c, n, part ? kFixT | kFixAlpha : kFixT, nullptr);
+        for (int i = 0; i < n_T && !rc; ++i) {
+            int32_t got = 0;
+            rc = mpr_get_trace(c, i, n, tr.data(), &got);
+            if (!rc && got != n) rc = MPR_EHIP;
+            if (rc) break;
+            if (trace_host)
+                std::memcpy(trace_host + ((size_t)i * total + (part ? n_burn : 0)) * 4, tr.data(),
+                            (size_t)n * 4 * sizeof(double));
+            if (part) {
+                double s = 0.0;
+                for (int32_t t = 0; t < n; ++t) s += tr[(size_t)t * 4];
+                e_host[i] = s / (double)n;
+            }
+        }
+    }
+    mpr_destroy(c);
+    if (d_z) (void)hipFree(d_z);
+    if (d_m) (void)hipFree(d_m);
+    return rc;
 }
 
 int mpr_set_temperature(mpr_ctx* c, double T)

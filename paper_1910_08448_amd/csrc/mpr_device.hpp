@@ -56,7 +56,10 @@ struct RunCtl {            // per context, device resident
     int64_t trace_base;    // sweep index of trace entry 0 = first sweep of the inference
     int64_t trace_cap;     // trace entries per (grid, chain)
     int64_t n_infer;       // sweeps of the current inference: [trace_base, trace_base + n_infer)
+    int64_t fixed;         // kFixT: the temperature stays (equilibration at a given T);
+                           // kFixAlpha: the window stays too (measurement sweeps)
 };
+constexpr int kFixT = 1, kFixAlpha = 2;
 
 // Inference sweeps in double-precision energy carry their own temperature control: sweep t of
 // an inference adds its exact integer sums (energy words, accepted moves) into slot t % 3 of the
@@ -435,10 +438,12 @@ __host__ __device__ inline double fix2_value(int64_t hi, int64_t lo)
 // energy matching and the acceptance-driven window): e_sim from the exact bond-energy sum, T
 // moved by the clamped ratio (e_smp + J) / (e_sim + J), alpha by A / A_target.  `c` holds the
 // state used by the sweep and becomes the state of the next one; tr (if not null) receives the
-// sweep's trace entry (e_sim, T, alpha, A).
+// sweep's trace entry (e_sim, T, alpha, A).  `fixed` (kFixT, kFixAlpha bits) keeps T and / or
+// alpha where they are.
 __device__ inline void control_step(GcCtl& c, double e_sim, int64_t n_acc, const GcDesc& g,
                                     bool second_half, double J, double acc_target, double T_min,
-                                    double T_max, double r_single, bool use_single, double* tr)
+                                    double T_max, double r_single, bool use_single, double* tr,
+                                    int64_t fixed)
 {
     const double A = g.n_pred > 0 ? (double)n_acc * g.inv_n_pred : acc_target;
     double r;
@@ -450,8 +455,8 @@ __device__ inline void control_step(GcCtl& c, double e_sim, int64_t n_acc, const
     if (tr) { tr[0] = e_sim; tr[1] = c.T; tr[2] = c.alpha; tr[3] = A; }
     if (second_half) { c.T_sum += c.T; c.T_cnt += 1; }
     r = fmin(fmax(r, 0.5), 2.0);
-    c.T = fmin(fmax(c.T * r, T_min), T_max);
-    c.alpha = fmin(fmax(c.alpha * (A / acc_target), 1e-3), 1.0);
+    if (!(fixed & kFixT)) c.T = fmin(fmax(c.T * r, T_min), T_max);
+    if (!(fixed & kFixAlpha)) c.alpha = fmin(fmax(c.alpha * (A / acc_target), 1e-3), 1.0);
     c.e_sim = e_sim;
     c.acc_rate = A;
 }
@@ -545,7 +550,8 @@ __device__ inline GcCtl sweep_control(bool fused, bool apply, int gc, const GcDe
     na = wave_sum_i64(na);
     double* tr = (lead && lane == 0) ? trace + ((int64_t)gc * run->trace_cap + (tm - 1)) * 4 : nullptr;
     control_step(c, -J * fix2_value(eh, el) * g.inv_n_bonds, na, g,
-                 s_abs - 1 >= run->s_half, J, acc_target, T_min, T_max, 0.0, false, tr);
+                 s_abs - 1 >= run->s_half, J, acc_target, T_min, T_max, 0.0, false, tr,
+                 run->fixed);
     if (lead) {
         if (lane == 0) ictl[(tm & 1) * n_gc + gc] = c;
         if (lane < kAccCopies) {

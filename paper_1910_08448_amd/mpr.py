@@ -54,6 +54,9 @@ _SIG = {
     "mpr_batch_load": (ctypes.c_int, [_vp, _vp, _vp]),
     "mpr_infer_temperature": (ctypes.c_int, [_vp, _i32, _vp]),
     "mpr_set_temperature": (ctypes.c_int, [_vp, _d]),
+    "mpr_equilibrate": (ctypes.c_int, [_vp, _i32, _vp]),
+    "mpr_energy_curve": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _i32, _i32, _vp, _vp]),
+    "mpr_set_temperature_curve": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp]),
     "mpr_burn_in": (ctypes.c_int, [_vp, _i32]),
     "mpr_run": (ctypes.c_int, [_vp, _i32]),
     "mpr_get_predictions": (ctypes.c_int, [_vp, _vp]),
@@ -192,6 +195,19 @@ class Context:
     def set_temperature(self, T):
         self._call("mpr_set_temperature", _lib.mpr_set_temperature, T)
 
+    def equilibrate(self, n, want_T=True):
+        T = np.zeros(self.n_grids * self.n_chains) if want_T else None
+        self._call("mpr_equilibrate", _lib.mpr_equilibrate, n, _ptr(T))
+        return T
+
+    def set_temperature_curve(self, T, e):
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        e = np.ascontiguousarray(e, dtype=np.float64)
+        out = np.zeros(self.n_grids * self.n_chains)
+        self._call("mpr_set_temperature_curve", _lib.mpr_set_temperature_curve, T.size, _ptr(T),
+                   _ptr(e), _ptr(out))
+        return out
+
     def burn_in(self, n):
         self._call("mpr_burn_in", _lib.mpr_burn_in, n)
 
@@ -244,6 +260,24 @@ class Context:
         d = t.empty(self.n_sites() * self.n_chains, dtype=t.uint8, device="cuda")
         self._call("mpr_debug_sweep", _lib.mpr_debug_sweep, sweep, _ptr(d))
         return d
+
+
+def energy_curve(side, T, n_burn, n_meas, with_trace=False, stream=None, **cfg):
+    """Mean bond energy e(T) of the data-free model on a periodic side x side lattice at each
+    temperature of T (host array); returns a numpy array (and the per-sweep trace
+    [n_T][n_burn + n_meas][4] if with_trace).  Runs on `stream` (torch's current stream if
+    None) and synchronises."""
+    import torch
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    e = np.zeros(T.size)
+    tr = np.zeros((T.size, n_burn + n_meas, 4)) if with_trace else None
+    st = stream if stream is not None else torch.cuda.current_stream()
+    c = default_config(**cfg)
+    rc = _lib.mpr_energy_curve(ctypes.byref(c), ctypes.c_void_p(st.cuda_stream), side, T.size,
+                               _ptr(T), n_burn, n_meas, _ptr(e), _ptr(tr))
+    if rc != OK:
+        raise MprError(rc, "mpr_energy_curve")
+    return (e, tr) if with_trace else e
 
 
 def predict(z, mask, n_equil, n_avg, stream=None, **cfg):

@@ -1,0 +1,142 @@
+"""GPU parity of the second temperature reading (the energy-temperature curve of the data-free
+model of Eq. (2), inverted at the sample energy) and of fixed-temperature equilibration, through
+the C ABI, against the FP64 oracle."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import oracle as O                      # noqa: E402
+from paper_1910_08448_amd import synth              # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def mpr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_08448_amd import mpr as M
+    return M
+
+
+def _dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def _ctx(mpr, w, **cfg):
+    ctx = mpr.Context(stream=torch.cuda.Stream(), **cfg)
+    ctx.load(_dev(w["z"], torch.float64), _dev(w["mask"], torch.uint8))
+    return ctx
+
+
+@pytest.mark.parametrize("side,q,J", [(32, 0.5, 1.0), (4, 0.5, 1.0), (48, 0.3, 1.7), (132, 0.5, 1.0)])
+def test_energy_curve_trace_matches_oracle(mpr, side, q, J):
+    """Every sweep's (e, T, alpha, acceptance) of every curve point, burn-in (window control)
+    and measurement (fixed window), and the curve itself; sides from one tile to several tiles
+    with a ragged last one."""
+    T = np.array([0.02, 0.3, 1.2]) * J
+    kw = dict(q=q, J=J, seed=41, alpha0=0.6, grid_offset=3)
+    eg, tg = mpr.energy_curve(side, T, 12, 10, with_trace=True, **kw)
+    okw = dict(kw)
+    okw["grid_id"] = okw.pop("grid_offset")
+    eo, to = O.energy_curve(side, T, 12, 10, with_trace=True, n_threads=4, **okw)
+    assert tg.shape == to.shape == (3, 22, 4)
+    assert np.allclose(tg, to, rtol=1e-9, atol=1e-13), np.abs(tg - to).max(axis=(0, 1))
+    assert np.allclose(eg, eo, rtol=1e-10, atol=1e-13)
+    assert np.all(tg[:, :, 1] == T[:, None])
+    assert np.all(tg[:, 12:, 2] == tg[:, 12:13, 2])     # the window stays during measurement
+
+
+def test_energy_curve_reduced_precision(mpr):
+    """FP32 and FP16 angle storage: the curve agrees with the FP64 oracle within its noise."""
+    T = np.array([0.05, 0.4, 1.5])
+    eo, to = O.energy_curve(64, T, 100, 200, with_trace=True, seed=8, n_threads=4)
+    # standard error of a 200-sweep mean from 10 batch means of the oracle's own trace
+    se = to[:, 100:, 0].reshape(3, 10, 20).mean(axis=2).std(axis=1, ddof=1) / np.sqrt(10)
+    for prec in (mpr.FP32, mpr.FP16):
+        eg = mpr.energy_curve(64, T, 100, 200, seed=8, precision=prec)
+        assert np.all(np.abs(eg - eo) < 6.0 * np.sqrt(2.0) * se + 1e-4 * (eo + 1.0)), (prec, eg, eo, se)
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_equilibrate_matches_oracle(mpr, mode):
+    w = synth.workload("grid64")
+    kw = dict(seed=w["mc_seed"], n_chains=2, alpha0=0.7)
+    ctx = _ctx(mpr, w, sweep_mode=mode, **kw)
+    orc = O.Oracle(n_threads=2, **kw)
+    orc.load(w["z"], w["mask"])
+    ctx.set_temperature(0.03)
+    orc.set_temperature(0.03)
+    Tg = ctx.equilibrate(40)
+    To = orc.equilibrate(40)
+    assert np.array_equal(Tg, To) and np.all(Tg == 0.03)
+    for ch in range(2):
+        assert np.allclose(ctx.trace(ch), orc.trace(ch), rtol=1e-9, atol=1e-13)
+    ctx.run(10)
+    orc.run(10)
+    zg = ctx.predictions().cpu().numpy().reshape(64, 64)
+    zo = orc.predictions()
+    m = w["mask"] == 0
+    assert np.abs(zg - zo)[m].mean() <= 1e-4 * np.ptp(w["z"][~m])
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_curve_temperature_method_matches_oracle(mpr, mode):
+    """Curve -> T-hat at the sample energy -> equilibration at T-hat -> averaging."""
+    w = synth.workload("grid64")
+    T = np.array([0.002, 0.005, 0.01, 0.02, 0.05, 0.1])
+    e = O.energy_curve(32, T, 200, 100, seed=5, n_threads=4)
+    kw = dict(seed=w["mc_seed"], n_chains=2)
+    ctx = _ctx(mpr, w, sweep_mode=mode, **kw)
+    orc = O.Oracle(n_threads=2, **kw)
+    orc.load(w["z"], w["mask"])
+    Tg = ctx.set_temperature_curve(T, e)
+    To = orc.set_temperature_curve(T, e)
+    assert np.allclose(Tg, To, rtol=1e-12, atol=0)
+    assert np.all(ctx.equilibrate(100) == Tg)
+    orc.equilibrate(100)
+    ctx.run(50)
+    orc.run(50)
+    zg = ctx.predictions().cpu().numpy().reshape(64, 64)
+    zo = orc.predictions()
+    m = w["mask"] == 0
+    assert np.abs(zg - zo)[m].mean() <= 1e-3 * np.ptp(w["z"][~m])
+
+
+def test_curve_kernel_inversion_cases(mpr):
+    """Clamping at both ends, the first bracket of a non-monotone curve, a flat segment."""
+    w = synth.workload("grid64")
+    ctx = _ctx(mpr, w)
+    e_smp = ctx.stats()[0]["e_sample"]
+    cases = [
+        ([0.1, 0.2], [e_smp + 0.1, e_smp + 0.2], 0.1),
+        ([0.1, 0.2], [e_smp - 0.2, e_smp - 0.1], 0.2),
+        ([0.3], [e_smp + 1.0], 0.3),
+        ([0.1, 0.2, 0.4], [e_smp - 0.1, e_smp, e_smp], 0.2),
+        ([0.1, 0.2, 0.4], [e_smp - 0.1, e_smp + 0.1, e_smp - 0.3], 0.15),
+    ]
+    for T, e, want in cases:
+        got = ctx.set_temperature_curve(T, e)[0]
+        assert got == pytest.approx(want, rel=1e-12)
+        assert got == O.curve_temperature(T, e, e_smp)
+
+
+def test_curve_error_codes(mpr):
+    for side, code in ((6, mpr.EINVAL), (7, mpr.EBIPARTITE)):
+        with pytest.raises(mpr.MprError) as ei:
+            mpr.energy_curve(side, [1.0], 1, 1)
+        assert ei.value.code == code
+    for T, nb, nm in (([0.0], 1, 1), ([np.inf], 1, 1), ([1.0], -1, 1), ([1.0], 1, 0)):
+        with pytest.raises(mpr.MprError) as ei:
+            mpr.energy_curve(8, T, nb, nm)
+        assert ei.value.code == mpr.EINVAL
+    w = synth.workload("grid64")
+    ctx = _ctx(mpr, w)
+    with pytest.raises(mpr.MprError) as ei:
+        ctx.equilibrate(3)
+    assert ei.value.code == mpr.ESTATE
+    with pytest.raises(mpr.MprError) as ei:
+        ctx.set_temperature_curve([0.2, 0.1], [-0.9, -0.8])
+    assert ei.value.code == mpr.EINVAL
+    ctx.set_temperature_curve([0.1, 0.2], [-0.9, -0.8])
+    ctx.equilibrate(3)                                    # now allowed
