@@ -55,7 +55,7 @@ def kernel_source_sha():
     """Digest of the sources the sweep kernel is built from."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("mpr_device.hpp", "mpr_sparse.hpp", "mpr.hip"):
+    for f in ("mpr_device.hpp", "mpr_sparse.hpp", "mpr_tiled.hpp", "mpr.hip"):
         with open(os.path.join(ROOT, "paper_1910_08448_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -116,7 +116,7 @@ def oracle_reference(name, p_missing):
     return json.load(open(path)).get(key)
 
 
-SWEEP_MODE = {"auto": 0, "fused": 1, "sparse": 2}
+SWEEP_MODE = {"auto": 0, "fused": 1, "sparse": 2, "tiled": 3}
 
 
 def measure(inp, precision, steps, warmup, kernel_launches, torch, M, sweep_mode="auto"):
@@ -170,9 +170,9 @@ def measure(inp, precision, steps, warmup, kernel_launches, torch, M, sweep_mode
         ev1.record(stream)
     ev1.synchronize()
     kernel_ms = ev0.elapsed_time(ev1) / kernel_launches
-    path = "sparse" if ctx.sweep_mode() == M.SWEEP_SPARSE else "fused"
-    kernel_name = ("k_sparse<colour 0> + k_sparse<colour 1> (inference variant, one sweep)"
-                   if path == "sparse" else "k_sweep (inference variant)")
+    path = {M.SWEEP_SPARSE: "sparse", M.SWEEP_TILED: "tiled"}.get(ctx.sweep_mode(), "fused")
+    kernel_name = {"sparse": "k_sparse<colour 0> + k_sparse<colour 1> (inference variant, one sweep)",
+                   "tiled": "k_tiled (inference variant)"}.get(path, "k_sweep (inference variant)")
     s = BYTES[precision]
     alg_bytes = sum((n + 2 * p) * s for n, p in zip(inp.n_sites, inp.n_pred)) * chains
     gbs = alg_bytes / (kernel_ms * 1e-3) / 1e9

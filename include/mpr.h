@@ -95,17 +95,25 @@ typedef struct mpr_config {
 /* How a sweep visits the sites.  FUSED: one launch per sweep over every site in row blocks,
  * both colours in one pass with halo recomputation; best when most sites are prediction sites.
  * SPARSE: two launches per sweep (one per colour) over lists of the prediction sites only, built
- * at load; best when a large share of the sites are samples.  Both take identical decisions from
- * identical states; their energy sums group the bonds differently, so temperature trajectories
- * agree to rounding, not bitwise.  SPARSE needs double-precision energy and grids with
- * H < 65536 and ceil(ceil(W / 2) / 2) * 2 < 65536.  AUTO picks SPARSE when it is possible and
- * either the functions are evaluated in double precision, at most 60 % of the sites are
- * prediction sites and sites x chains <= 2^25, or at most 40 % are prediction sites and
- * sites x chains <= 2^21 (measured crossovers on MI355X: the compacted path saves the lane work
- * of sample sites but evaluates four neighbour angles per site and launches twice per sweep);
- * FUSED otherwise.  The choice depends on the loaded data and configuration only and is fixed
+ * at load; best when a large share of the sites are samples.  TILED: one launch per sweep, one
+ * block per tile of 8 or 16 rows x 128 columns staged in LDS with its halo; each colour's
+ * prediction sites are compacted into a list inside the block, and the colour-0 sites around
+ * the tile are recomputed.  All three take identical decisions from identical states; SPARSE
+ * and TILED also sum the energy identically (bitwise equal results), while FUSED groups the
+ * bonds differently, so its temperature trajectories agree with theirs to rounding, not
+ * bitwise.  TILED needs double-precision energy.  SPARSE needs double-precision energy and grids with
+ * H < 65536 and ceil(ceil(W / 2) / 2) * 2 < 65536.  AUTO picks TILED when the energy is summed in
+ * double precision, the functions are evaluated in single precision and sites x chains <= 2^21
+ * (small grids, where a sweep is bound by latency: one launch instead of two); otherwise SPARSE
+ * when it is possible and either the functions are evaluated in double precision, at most 60 %
+ * of the sites are prediction sites and sites x chains <= 2^25, or at most 40 % are prediction
+ * sites and sites x chains <= 2^21 (measured crossovers on MI355X: the compacted path saves the
+ * lane work of sample sites but evaluates four neighbour angles per site and launches twice per
+ * sweep); FUSED otherwise.  The choice depends on the loaded data and configuration only and is fixed
  * for the context until the next load. */
-typedef enum mpr_sweep_mode { MPR_SWEEP_AUTO = 0, MPR_SWEEP_FUSED = 1, MPR_SWEEP_SPARSE = 2 } mpr_sweep_mode;
+typedef enum mpr_sweep_mode {
+    MPR_SWEEP_AUTO = 0, MPR_SWEEP_FUSED = 1, MPR_SWEEP_SPARSE = 2, MPR_SWEEP_TILED = 3
+} mpr_sweep_mode;
 
 /* Defaults: q = 1/2, J = 1, FP64 storage, open boundary, 1 chain, seed 1, alpha0 = 1,
  * acc_target = 0.3, T_min = 1e-6, T_max = 10, automatic tiles and graphs. */
@@ -236,7 +244,7 @@ int mpr_bench_sweeps(mpr_ctx* ctx, int32_t n);
  * tile_rows = -1 runs it at load (8 sweeps).  *rows_out (may be NULL) receives the choice. */
 int mpr_autotune(mpr_ctx* ctx, int32_t n_sweeps, int32_t* rows_out);
 
-/* The sweep path chosen at the last load (MPR_SWEEP_FUSED or MPR_SWEEP_SPARSE); ESTATE before
+/* The sweep path chosen at the last load (MPR_SWEEP_FUSED, _SPARSE or _TILED); ESTATE before
  * a load. */
 int mpr_get_sweep_mode(mpr_ctx* ctx, int32_t* mode_out);
 

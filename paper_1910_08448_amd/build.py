@@ -8,7 +8,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmpr.so")
 SOURCES = [os.path.join(CSRC, "mpr.hip")]
-HEADERS = [os.path.join(CSRC, "mpr_device.hpp"), os.path.join(ROOT, "include", "mpr.h")]
+HEADERS = [os.path.join(CSRC, f) for f in ("mpr_device.hpp", "mpr_sparse.hpp", "mpr_tiled.hpp")] + [
+    os.path.join(ROOT, "include", "mpr.h")]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -4,6 +4,7 @@
 #include "mpr.h"
 #include "mpr_device.hpp"
 #include "mpr_sparse.hpp"
+#include "mpr_tiled.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -218,8 +219,8 @@ __global__ void k_infer_begin(GcCtl* ctl, GcCtl* ictl, int64_t* gacc, const int6
         const int gc = (i / kAccCopies) % n_gc;
         const bool first = econst && (i % kAccCopies) == 0;   // copy 0 starts at the constant
         z[0] = first ? econst[2 * gc] : 0;
-        z[1] = first ? econst[2 * gc + 1] : 0;
-        z[2] = 0;
+        z[kAccWord] = first ? econst[2 * gc + 1] : 0;
+        z[2 * kAccWord] = 0;
     }
     if (i >= n_gc) return;
     GcCtl& c = ctl[i];
@@ -248,8 +249,8 @@ __global__ void k_infer_end(const GcDesc* gcs, GcCtl* ctl, const GcCtl* ictl, co
         int64_t eh = 0, el = 0, na = 0;
         for (int k = 0; k < kAccCopies; ++k) {
             eh += A[k * kAccStride];
-            el += A[k * kAccStride + 1];
-            na += A[k * kAccStride + 2];
+            el += A[k * kAccStride + kAccWord];
+            na += A[k * kAccStride + 2 * kAccWord];
         }
         const GcDesc g = gcs[i];
         control_step(c, -J * fix2_value(eh, el) * g.inv_n_bonds, na, g,
@@ -625,6 +626,23 @@ template <class S, class F> SparseFn pick_sparse(int flags, bool per, int colour
     return colour ? pick_sparse_c<S, F, false, 1>(flags) : pick_sparse_c<S, F, false, 0>(flags);
 }
 
+using TiledFn = void (*)(TiledArgs);
+
+template <class S, class F, bool PER> TiledFn pick_tiled_b(int flags)
+{
+    switch (flags) {
+    case 0: return k_tiled<S, F, 0, PER>;
+    case F_ENERGY: return k_tiled<S, F, F_ENERGY, PER>;
+    case F_ACC: return k_tiled<S, F, F_ACC, PER>;
+    default: return k_tiled<S, F, F_DEC, PER>;
+    }
+}
+
+template <class S, class F> TiledFn pick_tiled(int flags, bool per)
+{
+    return per ? pick_tiled_b<S, F, true>(flags) : pick_tiled_b<S, F, false>(flags);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ context
@@ -687,6 +705,12 @@ struct mpr_ctx {
     int64_t* d_econst = nullptr;                             // [n_gc][2]
     int32_t* d_rowcnt = nullptr;                             // scratch of the list build
     int64_t rowcnt_cap = 0, lead_cap[2] = {0, 0}, econst_cap = 0;
+    // LDS-tiled path (sweep_mode TILED): tiles of every (grid, chain), and the sample-sample
+    // bond energy (d_econst, shared with the compacted path)
+    bool tiled = false;
+    int4* d_tiles = nullptr;
+    int64_t tiles_cap = 0;
+    int32_t n_tiles = 0, tiles_ntx = 0;
 };
 
 static const char* kStatusText[] = {
@@ -732,8 +756,10 @@ static int check_config(const mpr_config* c)
     if (!(c->acc_target > 0.0 && c->acc_target < 1.0)) return MPR_EINVAL;
     if (!(c->T_min > 0.0) || !(c->T_max >= c->T_min) || !std::isfinite(c->T_max)) return MPR_EINVAL;
     if (c->tile_rows < -1 || c->grid_offset < 0) return MPR_EINVAL;
-    if (c->sweep_mode < MPR_SWEEP_AUTO || c->sweep_mode > MPR_SWEEP_SPARSE) return MPR_EINVAL;
-    if (c->sweep_mode == MPR_SWEEP_SPARSE && c->energy_prec == MPR_PREC_SINGLE) return MPR_EINVAL;
+    if (c->sweep_mode < MPR_SWEEP_AUTO || c->sweep_mode > MPR_SWEEP_TILED) return MPR_EINVAL;
+    if ((c->sweep_mode == MPR_SWEEP_SPARSE || c->sweep_mode == MPR_SWEEP_TILED) &&
+        c->energy_prec == MPR_PREC_SINGLE)
+        return MPR_EINVAL;
     return MPR_OK;
 }
 
@@ -752,13 +778,14 @@ static void free_device(mpr_ctx* c)
     c->d_trace = nullptr; c->d_flag = nullptr; c->d_ictl = nullptr; c->d_gacc = nullptr;
     c->trace_cap = 0;
     void* lists[] = {c->d_sites, c->d_waves[0], c->d_waves[1], c->d_lead[0], c->d_lead[1],
-                     c->d_econst, c->d_rowcnt};
+                     c->d_econst, c->d_rowcnt, c->d_tiles};
     for (void* p : lists)
         if (p) (void)hipFree(p);
     c->d_sites = nullptr; c->d_waves[0] = c->d_waves[1] = nullptr;
     c->d_lead[0] = c->d_lead[1] = nullptr; c->d_econst = nullptr; c->d_rowcnt = nullptr;
+    c->d_tiles = nullptr;
     c->sites_cap = c->waves_cap[0] = c->waves_cap[1] = c->rowcnt_cap = 0;
-    c->lead_cap[0] = c->lead_cap[1] = c->econst_cap = 0;
+    c->lead_cap[0] = c->lead_cap[1] = c->econst_cap = c->tiles_cap = 0;
     c->alloc_sig.clear();
 }
 
@@ -1000,6 +1027,42 @@ template <class S, class F> static void launch_econst(mpr_ctx* c)
     hipLaunchKernelGGL(fn, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_state[c->cur], c->cfg.q, c->d_econst);
 }
 
+static int build_econst(mpr_ctx* c);
+
+// tiles of the tiled path: per (grid, chain), row blocks of tile_rows x column blocks of
+// kTileCols plane columns, row-major (neighbouring tiles get neighbouring block numbers)
+template <class S, class F> static int build_tiles_t(mpr_ctx* c)
+{
+    constexpr int TY = tile_rows<S, F>();
+    std::vector<int4> t;
+    for (int i = 0; i < (int)c->gcs.size(); ++i) {
+        const GcDesc& d = c->gcs[i];
+        const int nty = (d.H + TY - 1) / TY, ntx = (d.wc + kTileCols - 1) / kTileCols;
+        if (i == 0) c->tiles_ntx = ntx;
+        for (int ty = 0; ty < nty; ++ty)
+            for (int tx = 0; tx < ntx; ++tx)
+                t.push_back(int4{i, ty * TY, tx * kTileCols, (ty == 0 && tx == 0) ? 1 : 0});
+        if (t.size() > (size_t)INT32_MAX) return fail(c, MPR_EINVAL, "too many tiles");
+    }
+    c->n_tiles = (int32_t)t.size();
+    if (c->gcs.size() > 1) {
+        int rc = ensure_buffer(c, (void**)&c->d_tiles, &c->tiles_cap, (int64_t)t.size() * sizeof(int4));
+        if (rc) return rc;
+        HIPCHK(c, h2d(c, c->d_tiles, t.data(), t.size() * sizeof(int4)));
+    }
+    return build_econst(c);
+}
+
+static int build_tiles(mpr_ctx* c)
+{
+    switch (c->sprec) {
+    case MPR_FP64: return c->fsingle ? build_tiles_t<double, float>(c) : build_tiles_t<double, double>(c);
+    case MPR_FP32: return c->fsingle ? build_tiles_t<float, float>(c) : build_tiles_t<float, double>(c);
+    case MPR_FIX16: return build_tiles_t<Fix15, float>(c);
+    default: return build_tiles_t<_Float16, float>(c);
+    }
+}
+
 // prediction-site lists of the compacted path, their waves, and the sample-sample bond energy
 static int build_lists(mpr_ctx* c)
 {
@@ -1073,7 +1136,15 @@ static int build_lists(mpr_ctx* c)
         HIPCHK(c, h2d(c, c->d_waves[col], waves[col].data(), waves[col].size() * sizeof(int2)));
         HIPCHK(c, h2d(c, c->d_lead[col], lead[col].data(), n_gc * sizeof(int32_t)));
     }
-    rc = ensure_buffer(c, (void**)&c->d_econst, &c->econst_cap, 2 * (int64_t)n_gc * sizeof(int64_t));
+    return build_econst(c);
+}
+
+// sample-sample bond energy per (grid, chain): seeds the accumulators of the compacted and
+// tiled paths, whose sweeps sum only bonds that touch a prediction site
+static int build_econst(mpr_ctx* c)
+{
+    const int n_gc = (int)c->gcs.size();
+    int rc = ensure_buffer(c, (void**)&c->d_econst, &c->econst_cap, 2 * (int64_t)n_gc * sizeof(int64_t));
     if (rc) return rc;
     HIPCHK(c, hipMemsetAsync(c->d_econst, 0, 2 * n_gc * sizeof(int64_t), c->stream));
     switch (c->sprec) {
@@ -1104,13 +1175,20 @@ static int choose_path(mpr_ctx* c)
     const double frac = (double)P / (double)N, work = (double)N * c->C;
     const bool prefer = c->fsingle ? (frac <= 0.4 && work <= 2097152.0)
                                    : (frac <= 0.6 && work <= 33554432.0);
-    const bool sparse = mode == MPR_SWEEP_SPARSE || (mode == MPR_SWEEP_AUTO && possible && prefer);
-    if (sparse != c->sparse) {                 // graphs hold the other path's kernels
+    if (mode == MPR_SWEEP_TILED && c->esingle)
+        return fail(c, MPR_EINVAL, "the tiled sweep needs double-precision energy");
+    // the tiled path wins where the single-precision sweep is latency-bound (one launch per
+    // sweep instead of two, no list reads): small grids with single-precision functions
+    const bool prefer_tiled = !c->esingle && c->fsingle && work <= 2097152.0;
+    const bool tiled = mode == MPR_SWEEP_TILED || (mode == MPR_SWEEP_AUTO && prefer_tiled);
+    const bool sparse = !tiled && (mode == MPR_SWEEP_SPARSE || (mode == MPR_SWEEP_AUTO && possible && prefer));
+    if (sparse != c->sparse || tiled != c->tiled) {   // graphs hold the other path's kernels
         for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
         c->graphs.clear();
     }
     c->sparse = sparse;
-    return sparse ? build_lists(c) : MPR_OK;
+    c->tiled = tiled;
+    return sparse ? build_lists(c) : (tiled ? build_tiles(c) : MPR_OK);
 }
 
 extern "C" {
@@ -1304,6 +1382,50 @@ static SweepFn sweep_fn(const mpr_ctx* c, int flags)
     }
 }
 
+static TiledFn tiled_fn(const mpr_ctx* c, int flags)
+{
+    const bool per = c->cfg.boundary == MPR_PERIODIC;
+    switch (c->sprec) {
+    case MPR_FP64: return c->fsingle ? pick_tiled<double, float>(flags, per) : pick_tiled<double, double>(flags, per);
+    case MPR_FP32: return c->fsingle ? pick_tiled<float, float>(flags, per) : pick_tiled<float, double>(flags, per);
+    case MPR_FIX16: return pick_tiled<Fix15, float>(flags, per);
+    default: return pick_tiled<_Float16, float>(flags, per);
+    }
+}
+
+// one sweep of the tiled path: every tile of every (grid, chain), src_buf -> the other buffer
+static void enqueue_tiled(mpr_ctx* c, int flags, int sweep_off, int src_buf, const RunCtl* run,
+                          uint8_t* dec)
+{
+    TiledArgs a{};
+    a.tiles = c->d_tiles;
+    a.gcs = c->d_gcs;
+    a.ctl = c->d_ctl;
+    a.run = run;
+    a.src = c->d_state[src_buf];
+    a.dst = c->d_state[1 - src_buf];
+    a.acc = c->d_acc;
+    a.dec = dec;
+    a.ictl = c->d_ictl;
+    a.gacc = c->d_gacc;
+    a.econst = c->d_econst;
+    a.trace = c->d_trace;
+    a.acc_target = c->cfg.acc_target;
+    a.T_min = c->cfg.T_min;
+    a.T_max = c->cfg.T_max;
+    a.q = c->cfg.q;
+    a.J = c->cfg.J;
+    a.n_gc = (int32_t)c->gcs.size();
+    a.n_tiles = c->n_tiles;
+    a.sweep_off = sweep_off;
+    a.key0 = (uint32_t)(c->cfg.seed & 0xffffffffu);
+    a.key1 = (uint32_t)(c->cfg.seed >> 32);
+    a.single = c->gcs.size() == 1;
+    a.ntx = c->tiles_ntx;
+    hipLaunchKernelGGL(tiled_fn(c, flags), dim3((unsigned)c->n_tiles), dim3(kWave * kTileWaves), 0,
+                       c->stream, a);
+}
+
 static SparseFn sparse_fn(const mpr_ctx* c, int flags, int colour)
 {
     const bool per = c->cfg.boundary == MPR_PERIODIC;
@@ -1361,6 +1483,10 @@ static void enqueue_sweep(mpr_ctx* c, int flags, int sweep_off, int src_buf, con
 {
     if (c->sparse) {
         enqueue_sparse(c, flags, sweep_off, run, dec);
+        return;
+    }
+    if (c->tiled) {
+        enqueue_tiled(c, flags, sweep_off, src_buf, run, dec);
         return;
     }
     SweepArgs a{};
@@ -1458,7 +1584,7 @@ static int infer_common(mpr_ctx* c, int32_t n_equil, int fixed, double* T_host)
         c->graphs.clear();
     }
     hipLaunchKernelGGL(k_infer_begin, dim3((3 * n_gc * kAccCopies + 255) / 256), dim3(256), 0, c->stream, c->d_ctl,
-                       c->d_ictl, c->d_gacc, c->sparse ? c->d_econst : nullptr, n_gc, c->cfg.J,
+                       c->d_ictl, c->d_gacc, (c->sparse || c->tiled) ? c->d_econst : nullptr, n_gc, c->cfg.J,
                        c->cfg.T_min, c->cfg.T_max, c->d_run,
                        (int64_t)(c->next_sweep + n_equil / 2), (int64_t)c->next_sweep,
                        (int64_t)c->trace_cap, (int64_t)n_equil, fixed);
@@ -1855,7 +1981,7 @@ static int use_rows(mpr_ctx* c, int rows)
 
 static int autotune(mpr_ctx* c, int n, int* best_out)
 {
-    if (c->sparse) {            // no work-item shape on the compacted path
+    if (c->sparse || c->tiled) {   // no work-item shape on the compacted and tiled paths
         if (best_out) *best_out = c->rows;
         return MPR_OK;
     }
@@ -1928,7 +2054,7 @@ int mpr_get_sweep_mode(mpr_ctx* c, int32_t* mode_out)
 {
     if (!c || !mode_out) return MPR_EINVAL;
     if (c->phase < PH_LOADED) return fail(c, MPR_ESTATE, "no data loaded");
-    *mode_out = c->sparse ? MPR_SWEEP_SPARSE : MPR_SWEEP_FUSED;
+    *mode_out = c->sparse ? MPR_SWEEP_SPARSE : (c->tiled ? MPR_SWEEP_TILED : MPR_SWEEP_FUSED);
     return MPR_OK;
 }
 

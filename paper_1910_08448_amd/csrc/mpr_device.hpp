@@ -67,13 +67,14 @@ constexpr int kFixT = 1, kFixAlpha = 2;
 // of sweep t - 1 from slot (t - 1) % 3 and the control state in slot (t - 1) & 1.  The first
 // item of each (grid, chain) stores the new state in slot t & 1, the trace entry of sweep t - 1,
 // and clears slot (t + 1) % 3 for the next sweep.  Kernel boundaries order all of it.  Atomics
-// on one cache line serialise, so a slot holds kAccCopies copies a line apart (a block adds its
-// LDS-reduced sums to copy blockIdx % kAccCopies) and readers sum the copies (exact integers:
-// the order does not matter).
-constexpr int kAccCopies = 16;
-constexpr int kAccStride = 32;     // int64 words between copies (256 bytes)
-constexpr int kAccPerGc = kAccCopies * kAccStride;   // words 0, 1, 2 of a copy: energy high,
-                                                     // energy low, accepted moves
+// on one cache line serialise (about 12 ns each), so a slot holds kAccCopies copies and each of
+// a copy's three words sits on a cache line of its own (a block adds its LDS-reduced sums to
+// copy blockIdx % kAccCopies) and readers sum the copies (exact integers: the order does not
+// matter).  One wave reads all copies, one per lane.
+constexpr int kAccCopies = 64;
+constexpr int kAccWord = 16;       // int64 words between the words of a copy (128 bytes)
+constexpr int kAccStride = 3 * kAccWord;             // words 0, kAccWord, 2 kAccWord of a copy:
+constexpr int kAccPerGc = kAccCopies * kAccStride;   // energy high, energy low, accepted moves
 
 enum { F_ENERGY = 1, F_ACC = 2, F_DEC = 4 };
 enum { DEC_OR = 1, DEC_ACCEPT = 2, DEC_OUTSIDE = 4 };
@@ -522,32 +523,57 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t x)
 // the control step of the previous sweep from its exact sums, by every wave alike; the lead
 // wave stores the result, the trace entry, and resets the accumulator slot after next, whose
 // copy 0 starts at econst[gc] if given) or read as stored by the kernel that applied it.
-__device__ inline GcCtl sweep_control(bool fused, bool apply, int gc, const GcDesc& g, bool lead,
-                                      int lane, const GcCtl* ctl, const RunCtl* run, GcCtl* ictl,
-                                      int64_t* gacc, const int64_t* econst, double* trace,
-                                      int n_gc, int64_t s_abs, double J, double acc_target,
-                                      double T_min, double T_max, int& acc_slot)
+// Split in two so a kernel can issue the loads (fetch) long before it needs the result
+// (finish); sweep_control does both.
+struct CtlFetch {
+    GcCtl c;               // the state to use, or to take the control step from
+    int64_t eh, el, na;    // this lane's copy of the previous sweep's sums (apply only)
+    int tm;                // sweep index within the inference
+    bool apply;            // the previous sweep's control step is applied here
+};
+
+__device__ inline CtlFetch sweep_control_fetch(bool fused, bool apply, int gc, int lane,
+                                               const GcCtl* ctl, const RunCtl* run,
+                                               const GcCtl* ictl, const int64_t* gacc, int n_gc,
+                                               int64_t s_abs, int& acc_slot)
 {
+    CtlFetch f;
+    f.eh = f.el = f.na = 0;
+    f.tm = 0;
+    f.apply = false;
     acc_slot = 0;
-    if (!fused) return ctl[gc];
+    if (!fused) { f.c = ctl[gc]; return f; }
     const int64_t t = s_abs - run->trace_base;
     const bool infer = (t >= 0) & (t < run->n_infer);
-    if (!infer) return ctl[gc];
+    if (!infer) { f.c = ctl[gc]; return f; }
     const int tm = (int)t;
+    f.tm = tm;
     acc_slot = tm % 3;
-    if (!apply || tm == 0) return ictl[(tm & 1) * n_gc + gc];
-    GcCtl c = ictl[((tm - 1) & 1) * n_gc + gc];
+    if (!apply || tm == 0) { f.c = ictl[(tm & 1) * n_gc + gc]; return f; }
+    f.apply = true;
+    f.c = ictl[((tm - 1) & 1) * n_gc + gc];
     const int64_t* A = gacc + ((int64_t)((tm - 1) % 3) * n_gc + gc) * kAccPerGc;
-    int64_t eh = 0, el = 0, na = 0;
     if (lane < kAccCopies) {
-        eh = A[lane * kAccStride];
-        el = A[lane * kAccStride + 1];
-        na = A[lane * kAccStride + 2];
+        f.eh = A[lane * kAccStride];
+        f.el = A[lane * kAccStride + kAccWord];
+        f.na = A[lane * kAccStride + 2 * kAccWord];
     }
-    // 16 nonzero lanes: each 21-bit limb total stays below 2^26 for any int64 word
-    eh = wave_sum_i64(eh);
-    el = wave_sum_i64(el);
-    na = wave_sum_i64(na);
+    return f;
+}
+
+__device__ inline GcCtl sweep_control_finish(const CtlFetch& f, int gc, const GcDesc& g, bool lead,
+                                             int lane, const RunCtl* run, GcCtl* ictl,
+                                             int64_t* gacc, const int64_t* econst, double* trace,
+                                             int n_gc, int64_t s_abs, double J, double acc_target,
+                                             double T_min, double T_max)
+{
+    if (!f.apply) return f.c;
+    const int tm = f.tm;
+    GcCtl c = f.c;
+    // 64 lanes: each 21-bit limb total stays below 2^27 for any int64 word
+    const int64_t eh = wave_sum_i64(f.eh);
+    const int64_t el = wave_sum_i64(f.el);
+    const int64_t na = wave_sum_i64(f.na);
     double* tr = (lead && lane == 0) ? trace + ((int64_t)gc * run->trace_cap + (tm - 1)) * 4 : nullptr;
     control_step(c, -J * fix2_value(eh, el) * g.inv_n_bonds, na, g,
                  s_abs - 1 >= run->s_half, J, acc_target, T_min, T_max, 0.0, false, tr,
@@ -557,11 +583,23 @@ __device__ inline GcCtl sweep_control(bool fused, bool apply, int gc, const GcDe
         if (lane < kAccCopies) {
             int64_t* z = gacc + ((int64_t)((tm + 1) % 3) * n_gc + gc) * kAccPerGc + lane * kAccStride;
             z[0] = (econst && lane == 0) ? econst[2 * gc] : 0;
-            z[1] = (econst && lane == 0) ? econst[2 * gc + 1] : 0;
-            z[2] = 0;
+            z[kAccWord] = (econst && lane == 0) ? econst[2 * gc + 1] : 0;
+            z[2 * kAccWord] = 0;
         }
     }
     return c;
+}
+
+__device__ inline GcCtl sweep_control(bool fused, bool apply, int gc, const GcDesc& g, bool lead,
+                                      int lane, const GcCtl* ctl, const RunCtl* run, GcCtl* ictl,
+                                      int64_t* gacc, const int64_t* econst, double* trace,
+                                      int n_gc, int64_t s_abs, double J, double acc_target,
+                                      double T_min, double T_max, int& acc_slot)
+{
+    const CtlFetch f = sweep_control_fetch(fused, apply, gc, lane, ctl, run, ictl, gacc, n_gc, s_abs,
+                                           acc_slot);
+    return sweep_control_finish(f, gc, g, lead, lane, run, ictl, gacc, econst, trace, n_gc, s_abs, J,
+                                acc_target, T_min, T_max);
 }
 
 // per-row data of one lane: (cos, sin) of both pair members, zero where the site is absent
@@ -913,14 +951,14 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
                 for (int k = 0; k < kWavesPerBlock; ++k) { s0 += red[k][0]; s1 += red[k][1]; s2 += red[k][2]; }
                 A += (blockIdx.x & (kAccCopies - 1)) * kAccStride;
                 atomicAdd(A, (unsigned long long)s0);
-                atomicAdd(A + 1, (unsigned long long)s1);
-                atomicAdd(A + 2, (unsigned long long)s2);
+                atomicAdd(A + kAccWord, (unsigned long long)s1);
+                atomicAdd(A + 2 * kAccWord, (unsigned long long)s2);
             }
         } else if (lane == 0) {
             A += (wid & (kAccCopies - 1)) * kAccStride;
             atomicAdd(A, (unsigned long long)e_hi);
-            atomicAdd(A + 1, (unsigned long long)e_lo);
-            atomicAdd(A + 2, (unsigned long long)(int64_t)n_acc);
+            atomicAdd(A + kAccWord, (unsigned long long)e_lo);
+            atomicAdd(A + 2 * kAccWord, (unsigned long long)(int64_t)n_acc);
         }
     } else if (lane == 0) {
         a.a_part[wid] = n_acc;

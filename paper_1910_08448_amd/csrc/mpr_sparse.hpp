@@ -204,14 +204,14 @@ __global__ __launch_bounds__(256) void k_sparse(SparseArgs a)
                 for (int i = 0; i < kWavesPerBlock; ++i) { s0 += red[i][0]; s1 += red[i][1]; s2 += red[i][2]; }
                 A += (blockIdx.x & (kAccCopies - 1)) * kAccStride;
                 atomicAdd(A, (unsigned long long)s0);
-                atomicAdd(A + 1, (unsigned long long)s1);
-                atomicAdd(A + 2, (unsigned long long)s2);
+                atomicAdd(A + kAccWord, (unsigned long long)s1);
+                atomicAdd(A + 2 * kAccWord, (unsigned long long)s2);
             }
         } else if (lane == 0) {
             A += (wid & (kAccCopies - 1)) * kAccStride;
             atomicAdd(A, (unsigned long long)e_hi);
-            atomicAdd(A + 1, (unsigned long long)e_lo);
-            atomicAdd(A + 2, (unsigned long long)(int64_t)n_acc);
+            atomicAdd(A + kAccWord, (unsigned long long)e_lo);
+            atomicAdd(A + 2 * kAccWord, (unsigned long long)(int64_t)n_acc);
         }
     }
 }

@@ -1,0 +1,342 @@
+// mpr_tiled.hpp -- the LDS-tiled checkerboard sweep for gfx950: one launch per sweep, one
+// block per tile of TY rows x kTileCols plane columns of both colour planes of one (grid,
+// chain).
+//
+// A block stages its tile with a halo in LDS: the colour-1 plane two rows / columns around it
+// (old values), the colour-0 plane one around it.  It updates the colour-0 prediction sites of
+// the tile and of the one-site ring around it (the ring repeats the neighbouring tiles' colour-0
+// updates bit for bit: same inputs, same counters), then, after one block barrier, the colour-1
+// prediction sites of the tile from the new colour-0 values.  Only prediction sites get lane
+// work: each colour's sites are compacted into an LDS list with wave ballots.  Every staged
+// value's (cos, sin) is evaluated once per tile, and an updated colour-0 site hands its new
+// (cos, sin) straight to its colour-1 neighbours.  The sweep reads the source buffer and writes
+// the tile's prediction sites into the destination buffer (sample values are equal in both).
+//
+// The field order ((left + right) + (up + down)), the site update, the Philox counters and the
+// energy split by bond kind (colour-1 prediction sites: all four bonds; colour-0 prediction
+// sites: bonds to colour-1 samples; sample-sample bonds: a constant of the data seeding the
+// accumulator) are those of the compacted path, so the two paths agree bit for bit.
+#pragma once
+
+#include "mpr_sparse.hpp"
+
+namespace mpr {
+
+constexpr int kTileCols = 64;                     // plane columns per tile (128 grid columns)
+constexpr int kTileWaves = 8;                     // waves per block (one block per tile)
+
+// rows per tile: 16 when a staged element (raw value and its (cos, sin)) takes at most 12
+// bytes, else 8, which keeps a block's LDS at 30-45 KB
+template <class S, class F> constexpr int tile_rows()
+{
+    return (sizeof(typename Store<S>::raw) + 2 * sizeof(F) <= 12) ? 16 : 8;
+}
+
+struct TiledArgs {
+    const int4* tiles;         // per tile (batched contexts): (gc, y0, k0, 1 if first of its gc)
+    const GcDesc* gcs;
+    const GcCtl* ctl;
+    const RunCtl* run;
+    const void* src;
+    void* dst;
+    double* acc;
+    uint8_t* dec;
+    GcCtl* ictl;
+    int64_t* gacc;
+    const int64_t* econst;     // per (grid, chain): sample-sample bond energy, two fixed-point words
+    double* trace;
+    double acc_target, T_min, T_max, q, J;
+    int32_t n_gc, n_tiles, sweep_off;
+    uint32_t key0, key1;
+    int32_t single;            // one (grid, chain): tile b sits at row block b / ntx, column block b % ntx
+    int32_t ntx;
+};
+
+template <class F> struct alignas(2 * sizeof(F)) CosSin { F c, s; };
+
+template <class S, class F, int FLAGS, bool PER>
+__global__ __launch_bounds__(kTileWaves * kWave) void k_tiled(TiledArgs a)
+{
+    using St = Store<S>;
+    using M = Math<F>;
+    using Raw = typename St::raw;
+    using CS = CosSin<F>;
+    constexpr int TY = tile_rows<S, F>(), TX = kTileCols;
+    constexpr int R1 = TY + 4, W1 = TX + 4;       // colour-1 stage: rows y0-2 ..., columns k0-2 ...
+    constexpr int R0 = TY + 2, W0 = TX + 2;       // colour-0 stage: rows y0-1 ..., columns k0-1 ...
+    constexpr int N1 = R1 * W1, N0 = R0 * W0;
+    constexpr int NW = kTileWaves, NT = kWave * NW;
+    // a stage is read in passes of one 64-column row segment per wave (rows wave, wave + NW, ...)
+    // plus one pass over the columns past the first 64 (4 for colour 1, 2 for colour 0)
+    constexpr int I1 = (R1 + NW - 1) / NW, I0 = (R0 + NW - 1) / NW;
+    constexpr int X1 = W1 - kWave, X0 = W0 - kWave;
+    static_assert(X1 * R1 <= NT && X0 * R0 <= NT, "one pass covers the extra columns");
+    // each wave compacts its prediction sites into its own list segment
+    constexpr int SEG1 = (I1 + 1) * kWave, SEG0 = (I0 + 1) * kWave;
+    constexpr uint32_t kRaw = (uint32_t)sizeof(Raw);
+    constexpr bool FUSED = (FLAGS & F_ENERGY) != 0;   // this path sums energies in double precision
+    // staged elements outside the grid: flagged as samples (never updated) with (cos, sin) = 0
+    constexpr Raw kAbsent = (Raw)((Raw)1 << (8 * sizeof(Raw) - 1));
+
+    __shared__ Raw raw1[N1];
+    __shared__ CS cs1[N1];
+    __shared__ Raw raw0[N0];
+    __shared__ CS cs0[N0];
+    __shared__ uint16_t list1[NW * SEG1], list0[NW * SEG0];
+    __shared__ int count[2][NW];
+    __shared__ double ctl_sh[2];
+    __shared__ int64_t red[NW][3];
+
+    const int tid = (int)threadIdx.x, lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lblock = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    int gc, y0, k0;
+    bool first;
+    if (a.single) {
+        gc = 0;
+        const int ty = lblock / a.ntx;
+        y0 = ty * TY;
+        k0 = (lblock - ty * a.ntx) * TX;
+        first = lblock == 0;
+    } else {
+        const int4 t = a.tiles[lblock];
+        gc = __builtin_amdgcn_readfirstlane(t.x);
+        y0 = __builtin_amdgcn_readfirstlane(t.y);
+        k0 = __builtin_amdgcn_readfirstlane(t.z);
+        first = __builtin_amdgcn_readfirstlane(t.w) != 0;
+    }
+
+    const GcDesc g = a.gcs[gc];
+    const int H = g.H, W = g.W, pitch = g.pitch, wc = g.wc;
+    const int ny = min(TY, H - y0), nk = min(TX, wc - k0);   // the tile proper, clipped to the grid
+    const int plane_sz = H * pitch;
+    const Rsrc rs = make_rsrc((const Raw*)a.src + g.plane_off, 2u * (uint32_t)plane_sz * kRaw);
+    const Rsrc rd = make_rsrc((Raw*)a.dst + g.plane_off, 2u * (uint32_t)plane_sz * kRaw);
+
+    // element (r, cc) of the stage of colour c with origin (y0 - h, k0 - h): its grid row and
+    // plane column (one wrap suffices: the stages stay within rows -2 .. H + 1 and columns
+    // -2 .. wc + 1, and periodic grids have H, wc >= 2), and whether it is a site to stage
+    auto locate = [&](int c, int h, int r, int cc, int& yy, int& kk) -> bool {
+        yy = y0 - h + r;
+        kk = k0 - h + cc;
+        bool ok = (r <= ny + 2 * h - 1) & (cc <= nk + 2 * h - 1);
+        if (PER) {
+            yy = yy < 0 ? yy + H : (yy >= H ? yy - H : yy);
+            kk = kk < 0 ? kk + wc : (kk >= wc ? kk - wc : kk);
+        } else {
+            ok &= (yy >= 0) & (yy < H) & (kk >= 0) & (2 * kk + ((yy + c) & 1) < W);
+        }
+        return ok;
+    };
+    // stage slot i of this thread: main passes i < I (row wave + NW i, column lane), then the
+    // extra-column pass (element tid of the X-wide strip); -1 if there is no such element
+    auto slot_rc = [&](int i, int I, int R, int X, int& r, int& cc) -> bool {
+        if (i < I) { r = wave + NW * i; cc = lane; return r < R; }
+        r = tid / X; cc = kWave + (tid - r * X); return tid < X * R;
+    };
+
+    // control state of this sweep (during an inference the previous sweep's control step,
+    // applied here): wave 0 evaluates it for the block (the first tile's wave 0 also stores it)
+    // and hands T and alpha over through LDS; its loads go out first, its arithmetic overlaps
+    // the stage loads
+    const int64_t s_abs = a.run->base_sweep + a.sweep_off;
+    const uint32_t sweep = (uint32_t)s_abs;
+    int acc_slot = 0;
+    CtlFetch cf;
+    if (wave == 0)
+        cf = sweep_control_fetch(FUSED, true, gc, lane, a.ctl, a.run, a.ictl, a.gacc, a.n_gc, s_abs, acc_slot);
+
+    // issue every stage load before anything waits on one
+    Raw v1[I1 + 1], v0[I0 + 1];
+    bool ok1[I1 + 1], ok0[I0 + 1];
+    int e1[I1 + 1], e0[I0 + 1];
+#pragma unroll
+    for (int i = 0; i <= I1; ++i) {
+        int r, cc, yy, kk;
+        const bool in = slot_rc(i, I1, R1, X1, r, cc);
+        ok1[i] = in && locate(1, 2, r, cc, yy, kk);
+        e1[i] = in ? r * W1 + cc : -1;
+        v1[i] = buf_load_one<St>(rs, ok1[i] ? (uint32_t)(plane_sz + yy * pitch + kk) * kRaw : kBufOOB);
+    }
+#pragma unroll
+    for (int i = 0; i <= I0; ++i) {
+        int r, cc, yy, kk;
+        const bool in = slot_rc(i, I0, R0, X0, r, cc);
+        ok0[i] = in && locate(0, 1, r, cc, yy, kk);
+        e0[i] = in ? r * W0 + cc : -1;
+        v0[i] = buf_load_one<St>(rs, ok0[i] ? (uint32_t)(yy * pitch + kk) * kRaw : kBufOOB);
+    }
+
+    if (wave == 0) {
+        const GcCtl ctl = sweep_control_finish(cf, gc, g, first, lane, a.run, a.ictl, a.gacc, a.econst,
+                                               a.trace, a.n_gc, s_abs, a.J, a.acc_target, a.T_min,
+                                               a.T_max);
+        if (lane == 0) { ctl_sh[0] = ctl.T; ctl_sh[1] = ctl.alpha; }
+    }
+    const F q = (F)a.q;
+
+    // stage: raw values and (cos, sin); each wave compacts its prediction sites (ballots and a
+    // running count) into its list segments
+    int n_mine1 = 0, n_mine0 = 0;
+#pragma unroll
+    for (int i = 0; i <= I1; ++i) {
+        const int e = e1[i];
+        const Raw v = ok1[i] ? v1[i] : kAbsent;
+        F s, c;
+        M::sincos_rev(q * St::template value<F>(v), s, c);
+        if (e >= 0) {
+            raw1[e] = v;
+            cs1[e] = CS{ok1[i] ? c : (F)0, ok1[i] ? s : (F)0};
+        }
+        const int r = e / W1, cc = e - r * W1;
+        const bool upd = ok1[i] & !St::sample(v) & (r >= 2) & (r <= ny + 1) & (cc >= 2) & (cc <= nk + 1);
+        const uint64_t m = __ballot(upd);
+        const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (upd) list1[wave * SEG1 + n_mine1 + below] = (uint16_t)e;
+        n_mine1 += __popcll(m);
+    }
+#pragma unroll
+    for (int i = 0; i <= I0; ++i) {
+        const int e = e0[i];
+        const Raw v = ok0[i] ? v0[i] : kAbsent;
+        F s, c;
+        M::sincos_rev(q * St::template value<F>(v), s, c);
+        if (e >= 0) {
+            raw0[e] = v;
+            cs0[e] = CS{ok0[i] ? c : (F)0, ok0[i] ? s : (F)0};
+        }
+        const bool upd = ok0[i] & !St::sample(v);
+        const uint64_t m = __ballot(upd);
+        const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (upd) list0[wave * SEG0 + n_mine0 + below] = (uint16_t)e;
+        n_mine0 += __popcll(m);
+    }
+    if (lane == 0) { count[0][wave] = n_mine0; count[1][wave] = n_mine1; }
+    __syncthreads();
+
+    const F J = (F)a.J;
+    const F inv_piq = (F)(1.0 / (3.14159265358979323846 * a.q));
+    const double T = ctl_sh[0];
+    const F alpha = (F)ctl_sh[1];
+    const F kexp = (sizeof(F) == 4) ? (F)(-1.4426950408889634 / T) : (F)(-1.0 / T);
+    // list position i -> (wave segment, entry), from the prefix sums of the segment lengths
+    int pre[2][NW + 1];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        pre[c][0] = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) pre[c][w + 1] = pre[c][w] + count[c][w];
+    }
+    auto entry = [&](const uint16_t* list, int seg, int c, int i) -> int {
+        int w = 0, base = 0;
+#pragma unroll
+        for (int k = 1; k < NW; ++k)
+            if (i >= pre[c][k]) { w = k; base = pre[c][k]; }
+        return list[w * seg + (i - base)];
+    };
+    const int n0 = pre[0][NW], n1 = pre[1][NW];
+
+    int n_acc = 0;
+    int64_t e_hi = 0, e_lo = 0;
+    const Rsrc ra = make_rsrc(a.acc + g.plane_off, 2u * (uint32_t)plane_sz * 8u);
+    auto accumulate = [&](uint32_t elem, Raw nv) {
+        const u32x2_t p = __builtin_amdgcn_raw_buffer_load_b64(ra, (int)(elem * 8u), 0, 0);
+        double d = __longlong_as_double((long long)(((uint64_t)p.y << 32) | p.x));
+        d += St::template value<double>(nv);
+        const uint64_t b = (uint64_t)__double_as_longlong(d);
+        u32x2_t w;
+        w.x = (uint32_t)b; w.y = (uint32_t)(b >> 32);
+        __builtin_amdgcn_raw_buffer_store_b64(w, ra, (int)(elem * 8u), 0, 0);
+    };
+
+    // colour 0: the tile and its ring, from the old colour-1 stage
+    for (int i = tid; i < n0; i += NT) {
+        const int e = entry(list0, SEG0, 0, i);
+        const int r = e / W0, cc = e - r * W0;
+        int yy = y0 - 1 + r, kk = k0 - 1 + cc;
+        if (PER) {
+            yy = yy < 0 ? yy + H : (yy >= H ? yy - H : yy);
+            kk = kk < 0 ? kk + wc : (kk >= wc ? kk - wc : kk);
+        }
+        const int p = yy & 1;
+        const int b1 = (r + 1) * W1 + cc + 1;                 // same site in colour-1 stage coordinates
+        const int il = b1 + p - 1, ir = b1 + p, iu = b1 - W1, id = b1 + W1;
+        const CS nl = cs1[il], nr = cs1[ir], nu = cs1[iu], nd = cs1[id];
+        const F Cf = (nl.c + nr.c) + (nu.c + nd.c);
+        const F Sf = (nl.s + nr.s) + (nu.s + nd.s);
+        const Raw v = raw0[e];
+        const U4 rn = philox10(U4{(uint32_t)(yy * g.np + (kk >> 1)), sweep, (uint32_t)g.chain_word, 0u},
+                               a.key0, a.key1);
+        const uint32_t wa = (kk & 1) ? rn.z : rn.x, wb = (kk & 1) ? rn.w : rn.y;
+        const SiteOut<S, F> o = hybrid_update<S, F>(St::template value<F>(v), true, Cf, Sf, q, inv_piq, J,
+                                                    kexp, alpha, wa, wb);
+        cs0[e] = CS{o.c, o.s};
+        const bool own = (r >= 1) & (r <= ny) & (cc >= 1) & (cc <= nk);
+        if (own) {
+            const Raw nv = St::template encode<F>(o.u);
+            const uint32_t elem = (uint32_t)(yy * pitch + kk);
+            buf_store_one<St>(rd, elem * kRaw, nv);
+            n_acc += (o.dec >> 1) & 1;
+            if (FLAGS & F_ENERGY) {        // bonds to colour-1 samples only
+                const bool ml = St::sample(raw1[il]), mr = St::sample(raw1[ir]);
+                const bool mu = St::sample(raw1[iu]), md = St::sample(raw1[id]);
+                const F Cs = ((ml ? nl.c : (F)0) + (mr ? nr.c : (F)0)) + ((mu ? nu.c : (F)0) + (md ? nd.c : (F)0));
+                const F Ss = ((ml ? nl.s : (F)0) + (mr ? nr.s : (F)0)) + ((mu ? nu.s : (F)0) + (md ? nd.s : (F)0));
+                const Fix2 f = fixed64x2((double)M::fma(o.c, Cs, o.s * Ss));
+                e_hi += f.hi;
+                e_lo += f.lo;
+            }
+            if (FLAGS & F_ACC) accumulate(elem, nv);
+            if (FLAGS & F_DEC) a.dec[g.site_off + (int64_t)yy * W + 2 * kk + p] = (uint8_t)o.dec;
+        }
+    }
+    __syncthreads();
+
+    // colour 1: the tile, from the new colour-0 stage
+    for (int i = tid; i < n1; i += NT) {
+        const int e = entry(list1, SEG1, 1, i);
+        const int r = e / W1, cc = e - r * W1;
+        const int yy = y0 - 2 + r, kk = k0 - 2 + cc;          // inside the grid: no wrap
+        const int p = (yy + 1) & 1;
+        const int b0 = (r - 1) * W0 + cc - 1;                 // same site in colour-0 stage coordinates
+        const CS nl = cs0[b0 + p - 1], nr = cs0[b0 + p], nu = cs0[b0 - W0], nd = cs0[b0 + W0];
+        const F Cf = (nl.c + nr.c) + (nu.c + nd.c);
+        const F Sf = (nl.s + nr.s) + (nu.s + nd.s);
+        const Raw v = raw1[e];
+        const U4 rn = philox10(U4{(uint32_t)(yy * g.np + (kk >> 1)), sweep, (uint32_t)g.chain_word, 1u},
+                               a.key0, a.key1);
+        const uint32_t wa = (kk & 1) ? rn.z : rn.x, wb = (kk & 1) ? rn.w : rn.y;
+        const SiteOut<S, F> o = hybrid_update<S, F>(St::template value<F>(v), true, Cf, Sf, q, inv_piq, J,
+                                                    kexp, alpha, wa, wb);
+        const Raw nv = St::template encode<F>(o.u);
+        const uint32_t elem = (uint32_t)(plane_sz + yy * pitch + kk);
+        buf_store_one<St>(rd, elem * kRaw, nv);
+        n_acc += (o.dec >> 1) & 1;
+        if (FLAGS & F_ENERGY) {
+            const Fix2 f = fixed64x2((double)M::fma(o.c, Cf, o.s * Sf));
+            e_hi += f.hi;
+            e_lo += f.lo;
+        }
+        if (FLAGS & F_ACC) accumulate(elem, nv);
+        if (FLAGS & F_DEC) a.dec[g.site_off + (int64_t)yy * W + 2 * kk + p] = (uint8_t)o.dec;
+    }
+
+    if (FUSED) {
+        n_acc = wave_sum_i32(n_acc);
+        e_hi = wave_sum_i64(e_hi);
+        e_lo = wave_sum_i64(e_lo);
+        if (lane == 0) { red[wave][0] = e_hi; red[wave][1] = e_lo; red[wave][2] = (int64_t)n_acc; }
+        __syncthreads();
+        if (tid == 0) {             // wave 0 holds the accumulator slot of this sweep
+            int64_t t0 = 0, t1 = 0, t2 = 0;
+            for (int w = 0; w < NW; ++w) { t0 += red[w][0]; t1 += red[w][1]; t2 += red[w][2]; }
+            unsigned long long* A = (unsigned long long*)(a.gacc + ((int64_t)acc_slot * a.n_gc + gc) * kAccPerGc) +
+                                    (blockIdx.x & (kAccCopies - 1)) * kAccStride;
+            atomicAdd(A, (unsigned long long)t0);
+            atomicAdd(A + kAccWord, (unsigned long long)t1);
+            atomicAdd(A + 2 * kAccWord, (unsigned long long)t2);
+        }
+    }
+}
+
+}  // namespace mpr

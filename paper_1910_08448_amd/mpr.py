@@ -17,7 +17,7 @@ FP64, FP32, FP16, FIX16 = 0, 1, 2, 3
 PREC_DEFAULT, PREC_DOUBLE, PREC_SINGLE = -1, 0, 1
 OPEN, PERIODIC = 0, 1
 DEC_OR, DEC_ACCEPT, DEC_OUTSIDE = 1, 2, 4
-SWEEP_AUTO, SWEEP_FUSED, SWEEP_SPARSE = 0, 1, 2
+SWEEP_AUTO, SWEEP_FUSED, SWEEP_SPARSE, SWEEP_TILED = 0, 1, 2, 3
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libmpr.so is not built (%s); run paper_1910_08448_amd/build.py" % LIB_PATH)

@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def kernel_source_sha():
     h = hashlib.sha256()
-    for f in ("mpr_device.hpp", "mpr_sparse.hpp", "mpr.hip"):
+    for f in ("mpr_device.hpp", "mpr_sparse.hpp", "mpr_tiled.hpp", "mpr.hip"):
         with open(os.path.join(ROOT, "paper_1910_08448_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -32,9 +32,13 @@ def kernel_source_sha():
 
 def _infer_sweep_kind(name):
     """Which inference-sweep kernel a dispatch is: 'fused' (k_sweep with energy sums in double
-    precision), 'sparse0' / 'sparse1' (the compacted path's colour kernels), or None."""
+    precision), 'tiled' (k_tiled), 'sparse0' / 'sparse1' (the compacted path's colour kernels),
+    or None."""
     if "k_sweep" in name and ("1, false" in name or "Li1ELb0" in name):
         return "fused"
+    if "k_tiled" in name and (", 1, false>" in name or ", 1, true>" in name or
+                              "Li1ELb0E" in name or "Li1ELb1E" in name):
+        return "tiled"
     if "k_sparse" in name:
         for c in (0, 1):
             if ", 1, false, %d>" % c in name or ", 1, true, %d>" % c in name or \
@@ -63,7 +67,7 @@ def _pmc_means(dirs):
         for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
             if _is_copy_probe(r):
                 name = "copy probe"
-            elif "k_sweep" in r["Kernel_Name"] or "k_sparse" in r["Kernel_Name"]:
+            elif any(k in r["Kernel_Name"] for k in ("k_sweep", "k_sparse", "k_tiled")):
                 name = r["Kernel_Name"][:70]
             else:
                 continue

@@ -58,7 +58,7 @@ def test_energy_curve_reduced_precision(mpr):
         assert np.all(np.abs(eg - eo) < 6.0 * np.sqrt(2.0) * se + 1e-4 * (eo + 1.0)), (prec, eg, eo, se)
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_equilibrate_matches_oracle(mpr, mode):
     w = synth.workload("grid64")
     kw = dict(seed=w["mc_seed"], n_chains=2, alpha0=0.7)
@@ -80,7 +80,7 @@ def test_equilibrate_matches_oracle(mpr, mode):
     assert np.abs(zg - zo)[m].mean() <= 1e-4 * np.ptp(w["z"][~m])
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_curve_temperature_method_matches_oracle(mpr, mode):
     """Curve -> T-hat at the sample energy -> equilibration at T-hat -> averaging."""
     w = synth.workload("grid64")

@@ -119,7 +119,7 @@ def _degenerate_sites(mask, before, after, boundary):
     return bad
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 @pytest.mark.parametrize("H,W,boundary,chains", [
     (2, 2, 0, 1), (3, 2, 0, 1), (2, 3, 0, 2), (5, 7, 0, 1), (2, 4, 1, 1), (4, 8, 1, 2),
     (6, 4, 1, 1), (1 + 2 * 60, 9, 0, 1), (3, 4 * 60 + 3, 0, 1)])
@@ -181,7 +181,7 @@ def test_fp64_predictions_match_oracle_grid64(mpr, p):
     assert np.array_equal(zg[~m], w["z"][~m])
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_predictions_invariant_to_tiles_and_graphs(mpr, mode):
     w = synth.workload("grid64")
     res = []
@@ -246,7 +246,7 @@ def test_batch_fp64_matches_oracle_per_grid(mpr):
         off += z.size
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_resume_is_bitwise_on_gpu(mpr, mode):
     w = synth.workload("grid64")
     kw = dict(seed=9, n_chains=2, precision=mpr.FP16, sweep_mode=mode)
@@ -355,10 +355,11 @@ def test_autotune_keeps_results(mpr):
     assert np.array_equal(res[0], res[1])
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_large_grid_trace_matches_oracle(mpr, mode):
     """Inference trace on a 512 x 1000 grid: several column strips and row blocks per chain
-    (fused path), several thousand waves per colour (compacted path)."""
+    (fused path), several thousand waves per colour (compacted path), 32 x 4 tiles with a
+    ragged last column of tiles (tiled path)."""
     truth, z, mask = _field(512, 1000, 9)
     kw = dict(seed=31, n_chains=1)
     ctx = _gpu_ctx(mpr, z, mask, sweep_mode=mode, **kw)
@@ -415,13 +416,14 @@ def test_precision_settings(mpr, name):
 
 
 # ---------------------------------------------------------------- compacted (sparse) sweep path
+@pytest.mark.parametrize("mode", [2, 3])
 @pytest.mark.parametrize("H,W,boundary,chains", [
     (64, 64, 0, 1), (37, 53, 0, 2), (16, 24, 1, 1), (2, 2, 0, 1), (2, 4, 1, 1), (3, 243, 0, 1),
-    (130, 244, 0, 1)])
-def test_sparse_fp64_decisions_and_angles_match_oracle(mpr, H, W, boundary, chains):
-    """The compacted path takes the oracle's decisions from identical states."""
+    (130, 244, 0, 1), (40, 300, 1, 2)])
+def test_sparse_fp64_decisions_and_angles_match_oracle(mpr, H, W, boundary, chains, mode):
+    """The compacted and tiled paths take the oracle's decisions from identical states."""
     mask, rounds = _decisions_case(mpr, H, W, boundary, chains, mpr.FP64, seed=H * 13 + W,
-                                   mode=mpr.SWEEP_SPARSE)
+                                   mode=mode)
     free = np.broadcast_to(mask == 0, rounds[0][0].shape)
     for dg, do, ug, uo in rounds:
         assert np.array_equal(dg[~free], do[~free]) and not dg[~free].any()
@@ -437,7 +439,7 @@ def test_sparse_and_fused_decisions_are_identical(mpr, precision):
     truth, z, mask = _field(H, W, 99)
     u0 = synth.random_state(2, mask, 5)
     out = []
-    for mode in (mpr.SWEEP_FUSED, mpr.SWEEP_SPARSE):
+    for mode in (mpr.SWEEP_FUSED, mpr.SWEEP_SPARSE, mpr.SWEEP_TILED):
         ctx = _gpu_ctx(mpr, z, mask, precision=precision, sweep_mode=mode, n_chains=2, seed=3,
                        alpha0=0.5)
         assert ctx.sweep_mode() == mode
@@ -445,15 +447,17 @@ def test_sparse_and_fused_decisions_are_identical(mpr, precision):
         ctx.set_temperature(0.05)
         decs = [ctx.debug_sweep(s).cpu().numpy() for s in (4, 5, 6)]
         out.append((decs, ctx.get_state()["u"].cpu().numpy()))
-    for a, b in zip(out[0][0], out[1][0]):
-        assert np.array_equal(a, b)
-    assert np.array_equal(out[0][1], out[1][1])
+    for other in out[1:]:
+        for a, b in zip(out[0][0], other[0]):
+            assert np.array_equal(a, b)
+        assert np.array_equal(out[0][1], other[1])
 
 
-def test_sparse_trace_matches_oracle(mpr):
+@pytest.mark.parametrize("mode", [2, 3])
+def test_sparse_trace_matches_oracle(mpr, mode):
     truth, z, mask = _field(48, 64, 17)
     kw = dict(seed=21, n_chains=2)
-    ctx = _gpu_ctx(mpr, z, mask, sweep_mode=mpr.SWEEP_SPARSE, **kw)
+    ctx = _gpu_ctx(mpr, z, mask, sweep_mode=mode, **kw)
     orc = O.Oracle(n_threads=4, **kw)
     orc.load(z, mask)
     Tg = ctx.infer_temperature(40)
@@ -464,12 +468,13 @@ def test_sparse_trace_matches_oracle(mpr):
     assert np.allclose(Tg, To, rtol=1e-9)
 
 
+@pytest.mark.parametrize("mode", [2, 3])
 @pytest.mark.parametrize("p", [0.33, 0.66])
-def test_sparse_predictions_match_oracle_grid64(mpr, p):
+def test_sparse_predictions_match_oracle_grid64(mpr, p, mode):
     w = synth.workload("grid64", p_missing=p)
     kw = dict(seed=w["mc_seed"], n_chains=2)
     zo, To = O.predict(w["z"], w["mask"], 256, 100, n_threads=4, **kw)
-    ctx = _gpu_ctx(mpr, w["z"], w["mask"], sweep_mode=mpr.SWEEP_SPARSE, **kw)
+    ctx = _gpu_ctx(mpr, w["z"], w["mask"], sweep_mode=mode, **kw)
     Tg = ctx.infer_temperature(256)
     ctx.run(100)
     zg = ctx.predictions().cpu().numpy().reshape(64, 64)
@@ -478,10 +483,11 @@ def test_sparse_predictions_match_oracle_grid64(mpr, p):
     assert np.abs(zg - zo).mean() <= 1e-3 * rng
 
 
-def test_sparse_batch_equals_single_grids(mpr):
-    shapes = [(40, 56), (33, 17), (64, 64)]
+@pytest.mark.parametrize("mode", [2, 3])
+def test_sparse_batch_equals_single_grids(mpr, mode):
+    shapes = [(40, 56), (33, 17), (64, 64), (20, 300)]
     fields = [_field(h, w, 300 + i) for i, (h, w) in enumerate(shapes)]
-    kw = dict(seed=8, n_chains=2, sweep_mode=mpr.SWEEP_SPARSE)
+    kw = dict(seed=8, n_chains=2, sweep_mode=mode)
     bctx = mpr.Context(shapes=shapes, stream=torch.cuda.Stream(), **kw)
     bctx.batch_load(_dev(np.concatenate([f[1].ravel() for f in fields]), torch.float64),
                     _dev(np.concatenate([f[2].ravel() for f in fields]), torch.uint8))
@@ -499,11 +505,11 @@ def test_sparse_batch_equals_single_grids(mpr):
 
 
 def test_automatic_path_choice(mpr):
-    """AUTO takes the compacted path for small grids with few prediction sites (at most 40 %
-    with single-precision functions, 60 % with double), when the energy is summed in double
-    precision; the fused path otherwise."""
-    for p, prec, esingle, want in [(0.33, mpr.FP32, False, mpr.SWEEP_SPARSE),
-                                   (0.5, mpr.FP32, False, mpr.SWEEP_FUSED),
+    """AUTO takes the tiled path for small grids with single-precision functions, the compacted
+    path for small grids with few prediction sites and double-precision functions, when the
+    energy is summed in double precision; the fused path otherwise."""
+    for p, prec, esingle, want in [(0.33, mpr.FP32, False, mpr.SWEEP_TILED),
+                                   (0.5, mpr.FP16, False, mpr.SWEEP_TILED),
                                    (0.5, mpr.FP64, False, mpr.SWEEP_SPARSE),
                                    (0.9, mpr.FP64, False, mpr.SWEEP_FUSED),
                                    (0.33, mpr.FP32, True, mpr.SWEEP_FUSED)]:
@@ -512,12 +518,12 @@ def test_automatic_path_choice(mpr):
                        energy_prec=mpr.PREC_SINGLE if esingle else mpr.PREC_DEFAULT)
         assert ctx.sweep_mode() == want, (p, prec, esingle)
     truth, z, mask = _field(64, 64, 5)
-    with pytest.raises(mpr.MprError):
-        _gpu_ctx(mpr, z, mask, precision=mpr.FP32, energy_prec=mpr.PREC_SINGLE,
-                 sweep_mode=mpr.SWEEP_SPARSE)
+    for mode in (mpr.SWEEP_SPARSE, mpr.SWEEP_TILED):
+        with pytest.raises(mpr.MprError):
+            _gpu_ctx(mpr, z, mask, precision=mpr.FP32, energy_prec=mpr.PREC_SINGLE, sweep_mode=mode)
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_other_q_and_J_match_oracle(mpr, mode):
     """q < 1/2 and J != 1 (Eq. (2)): decisions from identical states and the inference trace."""
     truth, z, mask = _field(40, 52, 61)
@@ -572,3 +578,29 @@ def test_sparse_colour_without_prediction_sites(mpr):
     m = (mask == 0).ravel()
     rng_z = np.nanmax(z) - np.nanmin(z)
     assert np.abs(zs - zf)[m].mean() <= 1e-6 * rng_z
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2, 3])
+def test_tiled_equals_sparse_bitwise(mpr, precision):
+    """The tiled path sums the energy by the same bond kinds and per-site terms as the compacted
+    path, so whole runs (temperature trajectories, estimates, predictions) agree bit for bit;
+    a batch of uneven grids with two chains each, open and periodic."""
+    for boundary, shapes in ((0, [(45, 70), (17, 300), (2, 3), (64, 64)]),
+                             (1, [(16, 24), (34, 264), (2, 4)])):
+        fields = [_field(h, w, 500 + i) for i, (h, w) in enumerate(shapes)]
+        z = np.concatenate([f[1].ravel() for f in fields])
+        m = np.concatenate([f[2].ravel() for f in fields])
+        res = []
+        for mode in (mpr.SWEEP_SPARSE, mpr.SWEEP_TILED):
+            ctx = mpr.Context(shapes=shapes, stream=torch.cuda.Stream(), seed=4, n_chains=2,
+                              precision=precision, boundary=boundary, sweep_mode=mode)
+            ctx.batch_load(_dev(z, torch.float64), _dev(m, torch.uint8))
+            assert ctx.sweep_mode() == mode
+            T = ctx.infer_temperature(24)
+            tr = [ctx.trace(i) for i in range(2 * len(shapes))]
+            ctx.run(6)
+            res.append((T, tr, ctx.predictions().cpu().numpy()))
+        assert np.array_equal(res[0][0], res[1][0])
+        for a, b in zip(res[0][1], res[1][1]):
+            assert np.array_equal(a, b)
+        assert np.array_equal(res[0][2], res[1][2])
