@@ -1422,6 +1422,7 @@ static void enqueue_tiled(mpr_ctx* c, int flags, int sweep_off, int src_buf, con
     a.key1 = (uint32_t)(c->cfg.seed >> 32);
     a.single = c->gcs.size() == 1;
     a.ntx = c->tiles_ntx;
+    a.g0 = c->gcs[0];
     hipLaunchKernelGGL(tiled_fn(c, flags), dim3((unsigned)c->n_tiles), dim3(kWave * kTileWaves), 0,
                        c->stream, a);
 }

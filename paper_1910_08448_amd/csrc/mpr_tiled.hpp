@@ -50,6 +50,9 @@ struct TiledArgs {
     uint32_t key0, key1;
     int32_t single;            // one (grid, chain): tile b sits at row block b / ntx, column block b % ntx
     int32_t ntx;
+    GcDesc g0;                 // one (grid, chain): its record, so no table read precedes the
+                               // loads (geometry only: a reload with the same shapes keeps
+                               // captured launches, so mask-dependent fields come from gcs)
 };
 
 template <class F> struct alignas(2 * sizeof(F)) CosSin { F c, s; };
@@ -106,33 +109,38 @@ __global__ __launch_bounds__(kTileWaves * kWave) void k_tiled(TiledArgs a)
         first = __builtin_amdgcn_readfirstlane(t.w) != 0;
     }
 
-    const GcDesc g = a.gcs[gc];
+    GcDesc g;
+    if (a.single) g = a.g0;
+    else g = a.gcs[gc];
     const int H = g.H, W = g.W, pitch = g.pitch, wc = g.wc;
     const int ny = min(TY, H - y0), nk = min(TX, wc - k0);   // the tile proper, clipped to the grid
     const int plane_sz = H * pitch;
     const Rsrc rs = make_rsrc((const Raw*)a.src + g.plane_off, 2u * (uint32_t)plane_sz * kRaw);
     const Rsrc rd = make_rsrc((Raw*)a.dst + g.plane_off, 2u * (uint32_t)plane_sz * kRaw);
 
-    // element (r, cc) of the stage of colour c with origin (y0 - h, k0 - h): its grid row and
-    // plane column (one wrap suffices: the stages stay within rows -2 .. H + 1 and columns
-    // -2 .. wc + 1, and periodic grids have H, wc >= 2), and whether it is a site to stage
-    auto locate = [&](int c, int h, int r, int cc, int& yy, int& kk) -> bool {
-        yy = y0 - h + r;
+    // Stage elements.  Main passes: row r = wave + NW i (wave-uniform), column cc = lane; one
+    // pass over the columns past the first 64: element tid of that strip.  The stage of colour
+    // c with origin (y0 - h, k0 - h) covers rows r <= ny + 2h - 1 and columns cc <= nk + 2h - 1;
+    // one wrap suffices for periodic grids (rows -2 .. H + 1, columns -2 .. wc + 1, H, wc >= 2).
+    // Column part (per lane, once): plane column, and whether it is a grid site in a row of
+    // parity 0 / 1; row part (per pass): grid row, whether it is in the grid, its parity.
+    auto col_info = [&](int h, int cc, int& kk, bool& ev, bool& od) {
         kk = k0 - h + cc;
-        bool ok = (r <= ny + 2 * h - 1) & (cc <= nk + 2 * h - 1);
+        const bool reg = cc <= nk + 2 * h - 1;
         if (PER) {
-            yy = yy < 0 ? yy + H : (yy >= H ? yy - H : yy);
             kk = kk < 0 ? kk + wc : (kk >= wc ? kk - wc : kk);
+            ev = od = reg;
         } else {
-            ok &= (yy >= 0) & (yy < H) & (kk >= 0) & (2 * kk + ((yy + c) & 1) < W);
+            ev = reg & (kk >= 0) & (2 * kk < W);
+            od = reg & (kk >= 0) & (2 * kk + 1 < W);
         }
-        return ok;
     };
-    // stage slot i of this thread: main passes i < I (row wave + NW i, column lane), then the
-    // extra-column pass (element tid of the X-wide strip); -1 if there is no such element
-    auto slot_rc = [&](int i, int I, int R, int X, int& r, int& cc) -> bool {
-        if (i < I) { r = wave + NW * i; cc = lane; return r < R; }
-        r = tid / X; cc = kWave + (tid - r * X); return tid < X * R;
+    auto row_info = [&](int c, int h, int r, int& yy, bool& rok, int& par) {
+        yy = y0 - h + r;
+        rok = r <= ny + 2 * h - 1;
+        if (PER) yy = yy < 0 ? yy + H : (yy >= H ? yy - H : yy);
+        else rok &= (yy >= 0) & (yy < H);
+        par = (yy + c) & 1;
     };
 
     // control state of this sweep (during an inference the previous sweep's control step,
@@ -147,28 +155,43 @@ __global__ __launch_bounds__(kTileWaves * kWave) void k_tiled(TiledArgs a)
         cf = sweep_control_fetch(FUSED, true, gc, lane, a.ctl, a.run, a.ictl, a.gacc, a.n_gc, s_abs, acc_slot);
 
     // issue every stage load before anything waits on one
+    int kk1, kx1, kk0, kx0;
+    bool ev1, od1, evx1, odx1, ev0, od0, evx0, odx0;
+    col_info(2, lane, kk1, ev1, od1);
+    col_info(1, lane, kk0, ev0, od0);
+    const int rx1 = tid / X1, cx1 = kWave + (tid - rx1 * X1);    // extra-column elements
+    const int rx0 = tid / X0, cx0 = kWave + (tid - rx0 * X0);
+    col_info(2, cx1, kx1, evx1, odx1);
+    col_info(1, cx0, kx0, evx0, odx0);
     Raw v1[I1 + 1], v0[I0 + 1];
     bool ok1[I1 + 1], ok0[I0 + 1];
-    int e1[I1 + 1], e0[I0 + 1];
 #pragma unroll
     for (int i = 0; i <= I1; ++i) {
-        int r, cc, yy, kk;
-        const bool in = slot_rc(i, I1, R1, X1, r, cc);
-        ok1[i] = in && locate(1, 2, r, cc, yy, kk);
-        e1[i] = in ? r * W1 + cc : -1;
+        const bool main = i < I1;
+        const int r = main ? wave + NW * i : rx1;
+        int yy, par;
+        bool rok;
+        row_info(1, 2, r, yy, rok, par);
+        const bool in = main ? r < R1 : tid < X1 * R1;
+        ok1[i] = in & rok & (par ? (main ? od1 : odx1) : (main ? ev1 : evx1));
+        const int kk = main ? kk1 : kx1;
         v1[i] = buf_load_one<St>(rs, ok1[i] ? (uint32_t)(plane_sz + yy * pitch + kk) * kRaw : kBufOOB);
     }
 #pragma unroll
     for (int i = 0; i <= I0; ++i) {
-        int r, cc, yy, kk;
-        const bool in = slot_rc(i, I0, R0, X0, r, cc);
-        ok0[i] = in && locate(0, 1, r, cc, yy, kk);
-        e0[i] = in ? r * W0 + cc : -1;
+        const bool main = i < I0;
+        const int r = main ? wave + NW * i : rx0;
+        int yy, par;
+        bool rok;
+        row_info(0, 1, r, yy, rok, par);
+        const bool in = main ? r < R0 : tid < X0 * R0;
+        ok0[i] = in & rok & (par ? (main ? od0 : odx0) : (main ? ev0 : evx0));
+        const int kk = main ? kk0 : kx0;
         v0[i] = buf_load_one<St>(rs, ok0[i] ? (uint32_t)(yy * pitch + kk) * kRaw : kBufOOB);
     }
 
     if (wave == 0) {
-        const GcCtl ctl = sweep_control_finish(cf, gc, g, first, lane, a.run, a.ictl, a.gacc, a.econst,
+        const GcCtl ctl = sweep_control_finish(cf, gc, a.gcs[gc], first, lane, a.run, a.ictl, a.gacc, a.econst,
                                                a.trace, a.n_gc, s_abs, a.J, a.acc_target, a.T_min,
                                                a.T_max);
         if (lane == 0) { ctl_sh[0] = ctl.T; ctl_sh[1] = ctl.alpha; }
@@ -178,18 +201,22 @@ __global__ __launch_bounds__(kTileWaves * kWave) void k_tiled(TiledArgs a)
     // stage: raw values and (cos, sin); each wave compacts its prediction sites (ballots and a
     // running count) into its list segments
     int n_mine1 = 0, n_mine0 = 0;
+    const bool lc1 = (lane >= 2) & (lane <= nk + 1), lcx1 = cx1 <= nk + 1;   // colour-1 list columns
 #pragma unroll
     for (int i = 0; i <= I1; ++i) {
-        const int e = e1[i];
+        const bool main = i < I1;
+        const int r = main ? wave + NW * i : rx1;
+        const bool in = main ? r < R1 : tid < X1 * R1;
+        if (main && !in) continue;                       // wave-uniform
+        const int e = r * W1 + (main ? lane : cx1);
         const Raw v = ok1[i] ? v1[i] : kAbsent;
         F s, c;
         M::sincos_rev(q * St::template value<F>(v), s, c);
-        if (e >= 0) {
+        if (in) {
             raw1[e] = v;
             cs1[e] = CS{ok1[i] ? c : (F)0, ok1[i] ? s : (F)0};
         }
-        const int r = e / W1, cc = e - r * W1;
-        const bool upd = ok1[i] & !St::sample(v) & (r >= 2) & (r <= ny + 1) & (cc >= 2) & (cc <= nk + 1);
+        const bool upd = ok1[i] & !St::sample(v) & (r >= 2) & (r <= ny + 1) & (main ? lc1 : lcx1);
         const uint64_t m = __ballot(upd);
         const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
         if (upd) list1[wave * SEG1 + n_mine1 + below] = (uint16_t)e;
@@ -197,11 +224,15 @@ __global__ __launch_bounds__(kTileWaves * kWave) void k_tiled(TiledArgs a)
     }
 #pragma unroll
     for (int i = 0; i <= I0; ++i) {
-        const int e = e0[i];
+        const bool main = i < I0;
+        const int r = main ? wave + NW * i : rx0;
+        const bool in = main ? r < R0 : tid < X0 * R0;
+        if (main && !in) continue;                       // wave-uniform
+        const int e = r * W0 + (main ? lane : cx0);
         const Raw v = ok0[i] ? v0[i] : kAbsent;
         F s, c;
         M::sincos_rev(q * St::template value<F>(v), s, c);
-        if (e >= 0) {
+        if (in) {
             raw0[e] = v;
             cs0[e] = CS{ok0[i] ? c : (F)0, ok0[i] ? s : (F)0};
         }
