@@ -147,6 +147,7 @@ def measure(inp, precision, steps, warmup, kernel_launches, torch, M, sweep_mode
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / steps
     value = updates_per_step * steps / elapsed
+    lattice_rate = sum(inp.n_sites) * chains * (n_equil + n_avg) * steps / elapsed
     log("%d steps of %s/%s: %.3f ms/step, %.4g site-updates/s"
         % (steps, inp.name, precision, ms_per_step, value))
 
@@ -190,13 +191,33 @@ def measure(inp, precision, steps, warmup, kernel_launches, torch, M, sweep_mode
     out = {"workload": inp.name, "precision": precision, "value": value,
            "unit": "site-updates/s", "ms_per_step": ms_per_step, "steps": steps,
            "grids": len(inp.shapes), "sites": sum(inp.n_sites), "prediction_sites": sum(inp.n_pred),
-           "chains": chains, "sweep_path": path, "n_equil": n_equil, "n_avg": n_avg, "mae": mae, "rmse": rmse,
+           "chains": chains, "sweep_path": path, "n_equil": n_equil, "n_avg": n_avg,
+           "lattice_site_rate": lattice_rate, "mae": mae, "rmse": rmse,
            "T_hat": T_hat[:4], "roofline": roofline}
     ref = oracle_reference(inp.name, inp.p_missing)
     if ref is not None and chains == ref["chains"]:
         out["oracle_mae"] = ref["mae"]
         out["mae_vs_oracle"] = mae / ref["mae"] - 1.0
     return out
+
+
+def streaming_copy_gbs(torch, mib=1024, reps=5):
+    """Achieved HBM bandwidth of a device-to-device copy (bytes read + written per second)."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    gbs = 2.0 * n * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    log("streaming copy: %.0f GB/s" % gbs)
+    return gbs
 
 
 def cpu_baseline(grid, seed, seconds):
@@ -220,7 +241,14 @@ def cpu_baseline(grid, seed, seconds):
     t = time.perf_counter()
     o2.infer_temperature(n)
     dt = time.perf_counter() - t
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": n_pred * n / dt, "unit": "site-updates/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model,
             "sample": "first %d inference sweeps of grid 0 (%dx%d, %d prediction sites), 1 chain, FP64"
                       % (n, grid["z"].shape[0], grid["z"].shape[1], n_pred)}
 
@@ -262,6 +290,7 @@ def main():
         torch.cuda.synchronize()
         log("copy probe: %d MiB read + %d MiB written" % (args.copy_probe_mib, args.copy_probe_mib))
         del a, b
+    copy_gbs = streaming_copy_gbs(torch)
     inputs = {args.workload: Inputs(args.workload, args.p_missing, torch)}
     prim = measure(inputs[args.workload], args.precision, args.steps, args.warmup,
                    args.kernel_launches, torch, M, args.sweep_mode)
@@ -303,9 +332,14 @@ def main():
         "cpu_baseline": cpu,
         "setups": setups,
     }
-    for k in ("oracle_mae", "mae_vs_oracle"):
+    for k in ("oracle_mae", "mae_vs_oracle", "lattice_site_rate"):
         if k in prim:
             out[k] = prim[k]
+    # the second HBM denominator: what a plain device-to-device copy achieves on this GPU
+    for r in [prim["roofline"]] + [u["roofline"] for u in setups]:
+        h = r["hbm"]
+        h["copy_gbs"] = round(copy_gbs, 1)
+        h["frac_of_copy"] = round(h["achieved"] / copy_gbs, 4)
     print(json.dumps(out), flush=True)
 
 

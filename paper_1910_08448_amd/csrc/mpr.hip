@@ -1115,6 +1115,13 @@ static int build_lists(mpr_ctx* c)
             return fail(c, MPR_EINVAL, "too many prediction sites for the compacted path");
     }
     if (entries > (int64_t)INT32_MAX) return fail(c, MPR_EINVAL, "too many prediction sites for the compacted path");
+    // captured sweeps hold the wave counts and list bases in their arguments: a reload with the
+    // same shapes but other lists must capture again
+    if (meta[G] != c->list_base0[0] || meta[G + 1] != c->list_base0[1] ||
+        (int64_t)waves[0].size() != c->n_waves[0] || (int64_t)waves[1].size() != c->n_waves[1]) {
+        for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+        c->graphs.clear();
+    }
     c->list_base0[0] = meta[G];
     c->list_base0[1] = meta[G + 1];
     rc = ensure_buffer(c, (void**)&c->d_sites, &c->sites_cap, entries * 4);

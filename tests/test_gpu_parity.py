@@ -604,3 +604,28 @@ def test_tiled_equals_sparse_bitwise(mpr, precision):
         for a, b in zip(res[0][1], res[1][1]):
             assert np.array_equal(a, b)
         assert np.array_equal(res[0][2], res[1][2])
+
+
+@pytest.mark.parametrize("mode", [1, 2, 3])
+@pytest.mark.parametrize("p_first,p_second", [(0.3, 0.6), (0.6, 0.3)])
+def test_reload_with_the_same_shape_matches_a_fresh_context(mpr, mode, p_first, p_second):
+    """A second load with the same shape keeps the buffers and may keep the captured sweep
+    graphs; the new data's mask-dependent quantities (prediction-site count, site lists, sample
+    energy) must still take effect: the run equals a fresh context's bit for bit, whether the
+    second mask has more or fewer prediction sites."""
+    a = _field(96, 136, 21, p=p_first)
+    b = _field(96, 136, 22, p=p_second)
+    kw = dict(seed=6, n_chains=2, precision=mpr.FP32, sweep_mode=mode, graph_sweeps=4)
+    ctx = _gpu_ctx(mpr, a[1], a[2], **kw)
+    ctx.infer_temperature(16)
+    ctx.run(8)
+    ctx.load(_dev(b[1], torch.float64), _dev(b[2], torch.uint8))
+    Tr = ctx.infer_temperature(16)
+    ctx.run(8)
+    fresh = _gpu_ctx(mpr, b[1], b[2], **kw)
+    Tf = fresh.infer_temperature(16)
+    fresh.run(8)
+    assert np.array_equal(Tr, Tf)
+    for ch in range(2):
+        assert np.array_equal(ctx.trace(ch), fresh.trace(ch))
+    assert np.array_equal(ctx.predictions().cpu().numpy(), fresh.predictions().cpu().numpy())
