@@ -23,7 +23,9 @@
 namespace mpr {
 
 constexpr int kTileCols = 64;                     // plane columns per tile (128 grid columns)
-constexpr int kTileWaves = 8;                     // waves per block (one block per tile)
+// waves per block (one block per tile): 8, or 4 with double-precision functions, whose
+// register footprint leaves three waves per SIMD
+template <class F> constexpr int tile_waves() { return sizeof(F) == 8 ? 4 : 8; }
 
 // rows per tile: 16 when a staged element (raw value and its (cos, sin)) takes at most 12
 // bytes, else 8, which keeps a block's LDS at 30-45 KB
@@ -58,7 +60,7 @@ struct TiledArgs {
 template <class F> struct alignas(2 * sizeof(F)) CosSin { F c, s; };
 
 template <class S, class F, int FLAGS, bool PER>
-__global__ __launch_bounds__(kTileWaves * kWave) void k_tiled(TiledArgs a)
+__global__ __launch_bounds__(tile_waves<F>() * kWave) void k_tiled(TiledArgs a)
 {
     using St = Store<S>;
     using M = Math<F>;
@@ -68,7 +70,7 @@ __global__ __launch_bounds__(kTileWaves * kWave) void k_tiled(TiledArgs a)
     constexpr int R1 = TY + 4, W1 = TX + 4;       // colour-1 stage: rows y0-2 ..., columns k0-2 ...
     constexpr int R0 = TY + 2, W0 = TX + 2;       // colour-0 stage: rows y0-1 ..., columns k0-1 ...
     constexpr int N1 = R1 * W1, N0 = R0 * W0;
-    constexpr int NW = kTileWaves, NT = kWave * NW;
+    constexpr int NW = tile_waves<F>(), NT = kWave * NW;
     // a stage is read in passes of one 64-column row segment per wave (rows wave, wave + NW, ...)
     // plus one pass over the columns past the first 64 (4 for colour 1, 2 for colour 0)
     constexpr int I1 = (R1 + NW - 1) / NW, I0 = (R0 + NW - 1) / NW;
@@ -90,6 +92,7 @@ __global__ __launch_bounds__(kTileWaves * kWave) void k_tiled(TiledArgs a)
     __shared__ double ctl_sh[2];
     __shared__ int64_t red[NW][3];
 
+    if (blockDim.x != NT) return;                    // launched for another variant: no work
     const int tid = (int)threadIdx.x, lane = tid & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lblock = xcd_block((int)blockIdx.x, (int)gridDim.x);
