@@ -262,7 +262,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=sorted(PREC))
     ap.add_argument("--p-missing", type=float, default=None)
     ap.add_argument("--sweep-mode", default="auto", choices=sorted(SWEEP_MODE),
-                    help="sweep path: automatic choice, fused row blocks, or compacted site lists")
+                    help="sweep path: automatic choice, fused row blocks, compacted site lists, or LDS tiles")
     ap.add_argument("--kernel-launches", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -169,7 +169,7 @@ class Context:
         return sum(h * w for h, w in self.shapes)
 
     def sweep_mode(self):
-        """The sweep path chosen at the last load: SWEEP_FUSED or SWEEP_SPARSE."""
+        """The sweep path chosen at the last load: SWEEP_FUSED, SWEEP_SPARSE or SWEEP_TILED."""
         m = ctypes.c_int32()
         self._chk(_lib.mpr_get_sweep_mode(self.h, ctypes.byref(m)), "mpr_get_sweep_mode")
         return m.value
