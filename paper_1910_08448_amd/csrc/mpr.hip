@@ -1430,6 +1430,7 @@ static void enqueue_tiled(mpr_ctx* c, int flags, int sweep_off, int src_buf, con
     a.single = c->gcs.size() == 1;
     a.ntx = c->tiles_ntx;
     a.g0 = c->gcs[0];
+    a.inv_piq = 1.0 / (3.14159265358979323846 * c->cfg.q);
     const int waves = (c->sprec == MPR_FP16 || c->sprec == MPR_FIX16 || c->fsingle) ? tile_waves<float>()
                                                                                      : tile_waves<double>();
     hipLaunchKernelGGL(tiled_fn(c, flags), dim3((unsigned)c->n_tiles), dim3(kWave * waves), 0,

@@ -48,6 +48,7 @@ struct TiledArgs {
     const int64_t* econst;     // per (grid, chain): sample-sample bond energy, two fixed-point words
     double* trace;
     double acc_target, T_min, T_max, q, J;
+    double inv_piq;            // 1 / (pi q), as the other sweep kernels evaluate it
     int32_t n_gc, n_tiles, sweep_off;
     uint32_t key0, key1;
     int32_t single;            // one (grid, chain): tile b sits at row block b / ntx, column block b % ntx
@@ -197,9 +198,12 @@ __global__ __launch_bounds__(tile_waves<F>() * kWave) void k_tiled(TiledArgs a)
         const GcCtl ctl = sweep_control_finish(cf, gc, a.gcs[gc], first, lane, a.run, a.ictl, a.gacc, a.econst,
                                                a.trace, a.n_gc, s_abs, a.J, a.acc_target, a.T_min,
                                                a.T_max);
-        if (lane == 0) { ctl_sh[0] = ctl.T; ctl_sh[1] = ctl.alpha; }
+        // the Boltzmann factor's scale as in the other sweep kernels: float path 2^(dE (-log2 e / T)),
+        // double path exp(dE (-1 / T)); every wave reads it after the barrier
+        if (lane == 0) { ctl_sh[0] = (sizeof(F) == 4) ? -1.4426950408889634 / ctl.T : -1.0 / ctl.T; ctl_sh[1] = ctl.alpha; }
     }
     const F q = (F)a.q;
+    const F inv_piq = (F)a.inv_piq;
 
     // stage: raw values and (cos, sin); each wave compacts its prediction sites (ballots and a
     // running count) into its list segments
@@ -249,10 +253,8 @@ __global__ __launch_bounds__(tile_waves<F>() * kWave) void k_tiled(TiledArgs a)
     __syncthreads();
 
     const F J = (F)a.J;
-    const F inv_piq = (F)(1.0 / (3.14159265358979323846 * a.q));
-    const double T = ctl_sh[0];
+    const F kexp = (F)ctl_sh[0];
     const F alpha = (F)ctl_sh[1];
-    const F kexp = (sizeof(F) == 4) ? (F)(-1.4426950408889634 / T) : (F)(-1.0 / T);
     // list position i -> (wave segment, entry), from the prefix sums of the segment lengths
     int pre[2][NW + 1];
 #pragma unroll
