@@ -72,3 +72,31 @@ def test_binding_refuses_missing_library(tmp_path):
     r = subprocess.run([sys.executable, "-c", "import paper_1910_08448_amd.mpr"], cwd=tmp_path,
                        capture_output=True, text=True)
     assert r.returncode != 0 and "libmpr.so is not built" in r.stderr
+
+
+def test_energy_curve_and_sweep_mode_host_validation(M):
+    """Argument checks that return before any device work: the energy curve's inputs and the
+    sweep-mode field of the configuration."""
+    h = ctypes.c_void_p()
+    for kw in [dict(sweep_mode=4), dict(sweep_mode=-1),
+               dict(sweep_mode=M.SWEEP_SPARSE, energy_prec=M.PREC_SINGLE),
+               dict(sweep_mode=M.SWEEP_TILED, energy_prec=M.PREC_SINGLE)]:
+        bad = M.default_config(**kw)
+        assert M.mpr_create(ctypes.byref(bad), None, ctypes.byref(h)) == M.EINVAL, kw
+    cfg = M.default_config()
+    T = (ctypes.c_double * 2)(0.5, 1.0)
+    e = (ctypes.c_double * 2)()
+    bad_T = [(ctypes.c_double * 1)(0.0), (ctypes.c_double * 1)(-1.0), (ctypes.c_double * 1)(float("nan")),
+             (ctypes.c_double * 1)(float("inf"))]
+    ref = ctypes.byref(cfg)
+    assert M.mpr_energy_curve(None, None, 8, 2, T, 1, 1, e, None) == M.EINVAL
+    assert M.mpr_energy_curve(ref, None, 8, 0, T, 1, 1, e, None) == M.EINVAL     # no temperature
+    assert M.mpr_energy_curve(ref, None, 8, 2, None, 1, 1, e, None) == M.EINVAL
+    assert M.mpr_energy_curve(ref, None, 8, 2, T, 1, 1, None, None) == M.EINVAL
+    assert M.mpr_energy_curve(ref, None, 8, 2, T, -1, 1, e, None) == M.EINVAL    # n_burn < 0
+    assert M.mpr_energy_curve(ref, None, 8, 2, T, 1, 0, e, None) == M.EINVAL     # n_meas < 1
+    assert M.mpr_energy_curve(ref, None, 8, 2, T, 2 ** 31 - 1, 1, e, None) == M.EINVAL
+    for b in bad_T:
+        assert M.mpr_energy_curve(ref, None, 8, 1, b, 1, 1, e, None) == M.EINVAL
+    for fn in (M.mpr_equilibrate, M.mpr_set_temperature_curve):
+        assert fn(None, *([1] + [None] * (fn.argtypes.__len__() - 2))) == M.EINVAL
