@@ -237,11 +237,16 @@ int mpr_debug_sweep(mpr_ctx* ctx, int32_t sweep, uint8_t* decisions_dev);
  * recorded on the context's stream.  Advances the state and the sweep index like burn-in. */
 int mpr_bench_sweeps(mpr_ctx* ctx, int32_t n);
 
-/* Picks the rows per work item of the sweep kernel by timing n_sweeps inference sweeps for each
- * candidate (4 ... 256) from the current state, which is restored afterwards; results do not
- * depend on the choice.  Winners are remembered per shape and precision in the process, and in
- * the text file named by the environment variable MPR_TUNE_CACHE if it is set.  mpr_config
- * tile_rows = -1 runs it at load (8 sweeps).  *rows_out (may be NULL) receives the choice. */
+/* Autotuner: times n_sweeps inference-variant sweeps of each candidate from the current state,
+ * which is restored after each, and keeps the fastest.  Candidates: the fused path's rows per
+ * work item (the six best of 2 ... 256 by a cost model; results do not depend on the choice),
+ * and, when the configuration's sweep_mode is MPR_SWEEP_AUTO, the sweep path itself (fused,
+ * compacted where possible, tiled where possible; mpr_get_sweep_mode reports the choice; the
+ * path changes only the rounding of the energy sums, see mpr_sweep_mode).  Winners are
+ * remembered per shape, precision, sweep_mode and percentage of prediction sites in the process,
+ * and in the text file named by the environment variable MPR_TUNE_CACHE if it is set.
+ * mpr_config tile_rows = -1 runs it at every load (8 sweeps; a remembered winner costs no
+ * timing).  *rows_out (may be NULL) receives the fused path's rows per work item. */
 int mpr_autotune(mpr_ctx* ctx, int32_t n_sweeps, int32_t* rows_out);
 
 /* The sweep path chosen at the last load (MPR_SWEEP_FUSED, _SPARSE or _TILED); ESTATE before

@@ -1165,30 +1165,40 @@ static int build_econst(mpr_ctx* c)
     return MPR_OK;
 }
 
-// the sweep path for the loaded data (sweep_mode, or the automatic rule)
-static int choose_path(mpr_ctx* c)
+// whether the compacted path can run this context (double-precision energy, 16-bit list
+// coordinates) and the tiled path (double-precision energy)
+static bool sparse_possible(const mpr_ctx* c)
 {
     bool possible = !c->esingle;
-    int64_t P = 0, N = 0;
     for (int g = 0; g < c->G; ++g) {
         const GcDesc& d = c->gcs[(size_t)g * c->C];
         possible = possible && d.H < 65536 && d.pitch < 65536;
+    }
+    return possible;
+}
+static bool tiled_possible(const mpr_ctx* c) { return !c->esingle; }
+
+// the automatic rule (measured crossovers, see include/mpr.h)
+static int auto_path(const mpr_ctx* c)
+{
+    int64_t P = 0, N = 0;
+    for (int g = 0; g < c->G; ++g) {
         P += c->gi[g].n_pred;
         N += c->H[g] * c->W[g];
     }
-    const int mode = c->cfg.sweep_mode;
-    if (mode == MPR_SWEEP_SPARSE && !possible)
-        return fail(c, MPR_EINVAL, "the compacted sweep needs double-precision energy and sides below 65536");
     const double frac = (double)P / (double)N, work = (double)N * c->C;
-    const bool prefer = c->fsingle ? (frac <= 0.4 && work <= 2097152.0)
-                                   : (frac <= 0.6 && work <= 33554432.0);
-    if (mode == MPR_SWEEP_TILED && c->esingle)
-        return fail(c, MPR_EINVAL, "the tiled sweep needs double-precision energy");
     // the tiled path wins where the single-precision sweep is latency-bound (one launch per
     // sweep instead of two, no list reads): small grids with single-precision functions
-    const bool prefer_tiled = !c->esingle && c->fsingle && work <= 2097152.0;
-    const bool tiled = mode == MPR_SWEEP_TILED || (mode == MPR_SWEEP_AUTO && prefer_tiled);
-    const bool sparse = !tiled && (mode == MPR_SWEEP_SPARSE || (mode == MPR_SWEEP_AUTO && possible && prefer));
+    if (tiled_possible(c) && c->fsingle && work <= 2097152.0) return MPR_SWEEP_TILED;
+    const bool prefer = c->fsingle ? (frac <= 0.4 && work <= 2097152.0)
+                                   : (frac <= 0.6 && work <= 33554432.0);
+    return (sparse_possible(c) && prefer) ? MPR_SWEEP_SPARSE : MPR_SWEEP_FUSED;
+}
+
+// switch the context to sweep path `path` (lists or tiles built for the loaded data)
+static int apply_path(mpr_ctx* c, int path)
+{
+    const bool sparse = path == MPR_SWEEP_SPARSE, tiled = path == MPR_SWEEP_TILED;
     if (sparse != c->sparse || tiled != c->tiled) {   // graphs hold the other path's kernels
         for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
         c->graphs.clear();
@@ -1196,6 +1206,22 @@ static int choose_path(mpr_ctx* c)
     c->sparse = sparse;
     c->tiled = tiled;
     return sparse ? build_lists(c) : (tiled ? build_tiles(c) : MPR_OK);
+}
+
+// the sweep path for the loaded data (sweep_mode, or the automatic rule)
+static int choose_path(mpr_ctx* c)
+{
+    const int mode = c->cfg.sweep_mode;
+    if (mode == MPR_SWEEP_SPARSE && !sparse_possible(c))
+        return fail(c, MPR_EINVAL, "the compacted sweep needs double-precision energy and sides below 65536");
+    if (mode == MPR_SWEEP_TILED && !tiled_possible(c))
+        return fail(c, MPR_EINVAL, "the tiled sweep needs double-precision energy");
+    return apply_path(c, mode == MPR_SWEEP_AUTO ? auto_path(c) : mode);
+}
+
+static int current_path(const mpr_ctx* c)
+{
+    return c->sparse ? MPR_SWEEP_SPARSE : (c->tiled ? MPR_SWEEP_TILED : MPR_SWEEP_FUSED);
 }
 
 extern "C" {
@@ -1969,11 +1995,18 @@ static std::map<std::string, int>& tune_cache()
 static std::string tune_key(const mpr_ctx* c)
 {
     uint64_t h = 1469598103934665603ull;
-    for (int g = 0; g < c->G; ++g)
+    int64_t P = 0, N = 0;
+    for (int g = 0; g < c->G; ++g) {
         for (int64_t v : {c->H[g], c->W[g]}) { h ^= (uint64_t)v; h *= 1099511628211ull; }
-    char buf[160];
-    std::snprintf(buf, sizeof buf, "s%d_f%d_e%d_b%d_c%d_g%d_%016llx", c->sprec, (int)c->fsingle,
-                  (int)c->esingle, c->cfg.boundary, c->C, c->G, (unsigned long long)h);
+        P += c->gi[g].n_pred;
+        N += c->H[g] * c->W[g];
+    }
+    // the path depends on the share of prediction sites: keyed to the percent
+    const int pct = N > 0 ? (int)std::lround(100.0 * (double)P / (double)N) : 0;
+    char buf[192];
+    std::snprintf(buf, sizeof buf, "s%d_f%d_e%d_b%d_c%d_g%d_m%d_p%d_%016llx", c->sprec, (int)c->fsingle,
+                  (int)c->esingle, c->cfg.boundary, c->C, c->G, c->cfg.sweep_mode, pct,
+                  (unsigned long long)h);
     return buf;
 }
 
@@ -1990,19 +2023,30 @@ static int use_rows(mpr_ctx* c, int rows)
     return MPR_OK;
 }
 
+// Times n inference-variant sweeps of each candidate from the current state (restored after
+// each) and keeps the fastest: the row count of the fused path's work items, and with
+// sweep_mode AUTO the sweep path itself (fused, compacted, tiled).  Results do not depend on
+// the row count (tested bitwise); the path changes only the rounding of the energy sums.
+// Winners are cached per shape, precision and share of prediction sites as path * 1000 + rows.
 static int autotune(mpr_ctx* c, int n, int* best_out)
 {
-    if (c->sparse || c->tiled) {   // no work-item shape on the compacted and tiled paths
+    const bool pick_path = c->cfg.sweep_mode == MPR_SWEEP_AUTO;
+    if (!pick_path && (c->sparse || c->tiled)) {   // no work-item shape on these paths
         if (best_out) *best_out = c->rows;
         return MPR_OK;
     }
     const std::string key = tune_key(c);
     auto& cache = tune_cache();
+    auto finish = [&](int path, int rows) -> int {
+        int rc = MPR_OK;
+        if (path == MPR_SWEEP_FUSED && rows != c->rows) rc = use_rows(c, rows);
+        if (!rc) rc = apply_path(c, path);
+        if (best_out) *best_out = c->rows;
+        return rc;
+    };
     auto hit = cache.find(key);
-    if (hit != cache.end()) {
-        if (best_out) *best_out = hit->second;
-        return use_rows(c, hit->second);
-    }
+    if (hit != cache.end()) return finish(hit->second / 1000, hit->second % 1000);
+
     int maxH = 0;
     for (int g = 0; g < c->G; ++g) maxH = std::max<int>(maxH, (int)c->H[g]);
     void* saved = nullptr;
@@ -2011,42 +2055,59 @@ static int autotune(mpr_ctx* c, int n, int* best_out)
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
-    // candidates: the six best row counts of the cost model
-    std::vector<std::pair<double, int>> ranked;
-    for (int r : kRowCandidates) {
-        if (r > maxH && r > 2) break;
-        ranked.push_back({rows_cost(c, r), r});
-    }
-    std::sort(ranked.begin(), ranked.end());
-    if (ranked.size() > 6) ranked.resize(6);
-    int best = c->rows;
-    float best_ms = 1e30f;
-    for (const auto& cand : ranked) {
-        const int r = cand.second;
-        int rc = use_rows(c, r);
-        if (rc) { (void)hipFree(saved); return rc; }
+    // one candidate: n sweeps after a warm-up one, then the saved state back
+    auto time_sweeps = [&](float& ms) -> int {
         int buf = c->cur;
-        enqueue_sweep(c, F_ENERGY, 0, buf, c->d_run, nullptr);   // warm-up
-        buf ^= 1;
+        enqueue_sweep(c, F_ENERGY, 0, buf, c->d_run, nullptr);
+        buf ^= flips(c);
         HIPCHK(c, hipEventRecord(e0, c->stream));
-        for (int i = 0; i < n; ++i) { enqueue_sweep(c, F_ENERGY, 0, buf, c->d_run, nullptr); buf ^= 1; }
+        for (int i = 0; i < n; ++i) { enqueue_sweep(c, F_ENERGY, 0, buf, c->d_run, nullptr); buf ^= flips(c); }
         HIPCHK(c, hipEventRecord(e1, c->stream));
         HIPCHK(c, hipEventSynchronize(e1));
-        float ms = 0.0f;
         HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_ms) { best_ms = ms; best = r; }
         HIPCHK(c, hipMemcpyAsync(c->d_state[c->cur], saved, c->plane_elems * c->elem, hipMemcpyDeviceToDevice, c->stream));
+        return MPR_OK;
+    };
+    int best_path = current_path(c), best_rows = c->rows;
+    float best_ms = 1e30f;
+    int rc = MPR_OK;
+    // fused path: the six best row counts of the cost model
+    if (pick_path || best_path == MPR_SWEEP_FUSED) {
+        std::vector<std::pair<double, int>> ranked;
+        for (int r : kRowCandidates) {
+            if (r > maxH && r > 2) break;
+            ranked.push_back({rows_cost(c, r), r});
+        }
+        std::sort(ranked.begin(), ranked.end());
+        if (ranked.size() > 6) ranked.resize(6);
+        rc = apply_path(c, MPR_SWEEP_FUSED);
+        for (size_t k = 0; k < ranked.size() && !rc; ++k) {
+            float ms = 0.0f;
+            rc = use_rows(c, ranked[k].second);
+            if (!rc) rc = time_sweeps(ms);
+            if (!rc && ms < best_ms) { best_ms = ms; best_path = MPR_SWEEP_FUSED; best_rows = ranked[k].second; }
+        }
     }
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (pick_path) {
+        for (int path : {MPR_SWEEP_SPARSE, MPR_SWEEP_TILED}) {
+            if (rc) break;
+            if (path == MPR_SWEEP_SPARSE ? !sparse_possible(c) : !tiled_possible(c)) continue;
+            float ms = 0.0f;
+            rc = apply_path(c, path);
+            if (!rc) rc = time_sweeps(ms);
+            if (!rc && ms < best_ms) { best_ms = ms; best_path = path; }
+        }
+    }
+    (void)hipStreamSynchronize(c->stream);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipFree(saved);
-    cache[key] = best;
+    if (rc) return rc;
+    cache[key] = best_path * 1000 + best_rows;
     if (const char* path = std::getenv("MPR_TUNE_CACHE")) {
-        if (FILE* f = std::fopen(path, "a")) { std::fprintf(f, "%s %d\n", key.c_str(), best); std::fclose(f); }
+        if (FILE* f = std::fopen(path, "a")) { std::fprintf(f, "%s %d\n", key.c_str(), cache[key]); std::fclose(f); }
     }
-    if (best_out) *best_out = best;
-    return use_rows(c, best);
+    return finish(best_path, best_rows);
 }
 
 int mpr_autotune(mpr_ctx* c, int32_t n_sweeps, int32_t* rows_out)
@@ -2065,7 +2126,7 @@ int mpr_get_sweep_mode(mpr_ctx* c, int32_t* mode_out)
 {
     if (!c || !mode_out) return MPR_EINVAL;
     if (c->phase < PH_LOADED) return fail(c, MPR_ESTATE, "no data loaded");
-    *mode_out = c->sparse ? MPR_SWEEP_SPARSE : (c->tiled ? MPR_SWEEP_TILED : MPR_SWEEP_FUSED);
+    *mode_out = current_path(c);
     return MPR_OK;
 }
 

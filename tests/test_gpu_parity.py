@@ -629,3 +629,25 @@ def test_reload_with_the_same_shape_matches_a_fresh_context(mpr, mode, p_first, 
     for ch in range(2):
         assert np.array_equal(ctx.trace(ch), fresh.trace(ch))
     assert np.array_equal(ctx.predictions().cpu().numpy(), fresh.predictions().cpu().numpy())
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_autotuned_path_reproduces_the_chosen_path(mpr, precision):
+    """With sweep_mode AUTO and tile_rows = -1 the tuner times every possible sweep path at
+    load and keeps the fastest; the state it timed from is restored, so the tuned context
+    reproduces a fresh context forced onto the chosen path bit for bit, and a second load of
+    the same data takes the remembered choice."""
+    w = synth.workload("grid64", p_missing=0.5)
+    kw = dict(seed=5, precision=precision, n_chains=2)
+    tuned = _gpu_ctx(mpr, w["z"], w["mask"], tile_rows=-1, **kw)
+    mode = tuned.sweep_mode()
+    assert mode in (mpr.SWEEP_FUSED, mpr.SWEEP_SPARSE, mpr.SWEEP_TILED)
+    Tt = tuned.infer_temperature(30)
+    tuned.run(10)
+    forced = _gpu_ctx(mpr, w["z"], w["mask"], sweep_mode=mode, **kw)
+    Tf = forced.infer_temperature(30)
+    forced.run(10)
+    assert np.array_equal(Tt, Tf)
+    assert np.array_equal(tuned.predictions().cpu().numpy(), forced.predictions().cpu().numpy())
+    again = _gpu_ctx(mpr, w["z"], w["mask"], tile_rows=-1, **kw)
+    assert again.sweep_mode() == mode
