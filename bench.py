@@ -290,7 +290,8 @@ def main():
         torch.cuda.synchronize()
         log("copy probe: %d MiB read + %d MiB written" % (args.copy_probe_mib, args.copy_probe_mib))
         del a, b
-    copy_gbs = streaming_copy_gbs(torch)
+    # (a counter run with a copy probe skips it: its copies would mix with the probe's counts)
+    copy_gbs = streaming_copy_gbs(torch) if args.copy_probe_mib <= 0 else None
     inputs = {args.workload: Inputs(args.workload, args.p_missing, torch)}
     prim = measure(inputs[args.workload], args.precision, args.steps, args.warmup,
                    args.kernel_launches, torch, M, args.sweep_mode)
@@ -338,8 +339,8 @@ def main():
     # the second HBM denominator: what a plain device-to-device copy achieves on this GPU
     for r in [prim["roofline"]] + [u["roofline"] for u in setups]:
         h = r["hbm"]
-        h["copy_gbs"] = round(copy_gbs, 1)
-        h["frac_of_copy"] = round(h["achieved"] / copy_gbs, 4)
+        h["copy_gbs"] = round(copy_gbs, 1) if copy_gbs else None
+        h["frac_of_copy"] = round(h["achieved"] / copy_gbs, 4) if copy_gbs else None
     print(json.dumps(out), flush=True)
 
 

@@ -47,8 +47,15 @@ def _infer_sweep_kind(name):
     return None
 
 
-def _is_copy_probe(row):
+def _is_copy(row):
     return "copyBuffer" in row["Kernel_Name"] and int(row["Grid_Size"]) > 100000
+
+
+def _probe_dispatch(rows):
+    """The copy probe is the first large device copy of the run (bench.py --copy-probe-mib
+    issues it before anything else)."""
+    ids = [int(r["Dispatch_Id"]) for r in rows if _is_copy(r)]
+    return min(ids) if ids else None
 
 
 def stats(d, top=10):
@@ -64,8 +71,12 @@ def stats(d, top=10):
 def _pmc_means(dirs):
     agg = collections.defaultdict(list)
     for d in dirs:
-        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
-            if _is_copy_probe(r):
+        rows = list(csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))))
+        probe = _probe_dispatch(rows)
+        for r in rows:
+            if _is_copy(r):
+                if int(r["Dispatch_Id"]) != probe:
+                    continue
                 name = "copy probe"
             elif any(k in r["Kernel_Name"] for k in ("k_sweep", "k_sparse", "k_tiled")):
                 name = r["Kernel_Name"][:70]
@@ -89,11 +100,14 @@ def traffic(fetch_dir, write_dir, copy_mib):
     res = {}
     for d, ctr in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
         kinds, probe = collections.defaultdict(list), []
-        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+        rows = list(csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))))
+        first = _probe_dispatch(rows)
+        for r in rows:
             if r["Counter_Name"] != ctr:
                 continue
-            if _is_copy_probe(r):
-                probe.append(float(r["Counter_Value"]))
+            if _is_copy(r):
+                if int(r["Dispatch_Id"]) == first:
+                    probe.append(float(r["Counter_Value"]))
             else:
                 k = _infer_sweep_kind(r["Kernel_Name"])
                 if k:
