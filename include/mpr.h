@@ -85,32 +85,35 @@ typedef struct mpr_config {
     double alpha0;            /* initial Metropolis window, fraction of a turn, (0, 1] */
     double acc_target;        /* acceptance rate the window control aims at, (0, 1)    */
     double T_min, T_max;      /* temperature clamp, 0 < T_min <= T_max                 */
-    int32_t tile_rows;        /* rows per work item, 0 = heuristic, -1 = autotune at load */
+    int32_t tile_rows;        /* rows per work item of the fused path, 0 = heuristic,
+                                 -1 = autotune at load (with sweep_mode AUTO also the
+                                 sweep path; see mpr_autotune)                       */
     int32_t graph_sweeps;     /* sweeps per captured HIP graph, 0 = automatic,
                                  -1 = launch kernels without graphs                   */
     int32_t sweep_mode;       /* mpr_sweep_mode: how a sweep visits the sites          */
     int32_t reserved[5];
 } mpr_config;
 
-/* How a sweep visits the sites.  FUSED: one launch per sweep over every site in row blocks,
- * both colours in one pass with halo recomputation; best when most sites are prediction sites.
+/* How a sweep visits the sites.
+ * FUSED: one launch per sweep over every site in row blocks, both colours in one pass with halo
+ *   recomputation; best when most sites are prediction sites and the grid is large.
  * SPARSE: two launches per sweep (one per colour) over lists of the prediction sites only, built
- * at load; best when a large share of the sites are samples.  TILED: one launch per sweep, one
- * block per tile of 8 or 16 rows x 128 columns staged in LDS with its halo; each colour's
- * prediction sites are compacted into a list inside the block, and the colour-0 sites around
- * the tile are recomputed.  All three take identical decisions from identical states; SPARSE
- * and TILED also sum the energy identically (bitwise equal results), while FUSED groups the
- * bonds differently, so its temperature trajectories agree with theirs to rounding, not
- * bitwise.  TILED needs double-precision energy.  SPARSE needs double-precision energy and grids with
- * H < 65536 and ceil(ceil(W / 2) / 2) * 2 < 65536.  AUTO picks TILED when the energy is summed in
- * double precision, the functions are evaluated in single precision and sites x chains <= 2^21
- * (small grids, where a sweep is bound by latency: one launch instead of two); otherwise SPARSE
- * when it is possible and either the functions are evaluated in double precision, at most 60 %
- * of the sites are prediction sites and sites x chains <= 2^25, or at most 40 % are prediction
- * sites and sites x chains <= 2^21 (measured crossovers on MI355X: the compacted path saves the
- * lane work of sample sites but evaluates four neighbour angles per site and launches twice per
- * sweep); FUSED otherwise.  The choice depends on the loaded data and configuration only and is fixed
- * for the context until the next load. */
+ *   at load; needs double-precision energy and grids with H < 65536 and
+ *   ceil(ceil(W / 2) / 2) * 2 < 65536.
+ * TILED: one launch per sweep, one block per tile of 8 or 16 rows x 128 columns staged in LDS
+ *   with its halo; each colour's prediction sites are compacted into a list inside the block,
+ *   and the colour-0 sites around the tile are recomputed; needs double-precision energy.
+ * All three take identical decisions from identical states; SPARSE and TILED also sum the
+ * energy identically (bitwise equal results), while FUSED groups the bonds differently, so its
+ * temperature trajectories agree with theirs to rounding, not bitwise.
+ * AUTO picks TILED when the energy is summed in double precision, the functions are evaluated
+ * in single precision and sites x chains <= 2^21 (small grids, where a sweep is bound by
+ * latency: one launch instead of two); otherwise SPARSE when it is possible and either the
+ * functions are evaluated in double precision, at most 60 % of the sites are prediction sites
+ * and sites x chains <= 2^25, or at most 40 % are prediction sites and sites x chains <= 2^21
+ * (measured crossovers on MI355X); FUSED otherwise.  The choice depends on the loaded data and
+ * configuration only (or, with tile_rows = -1, on the autotuner's timing) and is fixed for the
+ * context until the next load. */
 typedef enum mpr_sweep_mode {
     MPR_SWEEP_AUTO = 0, MPR_SWEEP_FUSED = 1, MPR_SWEEP_SPARSE = 2, MPR_SWEEP_TILED = 3
 } mpr_sweep_mode;
