@@ -107,7 +107,7 @@ typedef struct mpr_config {
  * energy identically (bitwise equal results), while FUSED groups the bonds differently, so its
  * temperature trajectories agree with theirs to rounding, not bitwise.
  * AUTO picks TILED when the energy is summed in double precision, the functions are evaluated
- * in single precision and sites x chains <= 2^21 (small grids, where a sweep is bound by
+ * in single precision and sites x chains <= 1.5 * 2^20 (small grids, where a sweep is bound by
  * latency: one launch instead of two); otherwise SPARSE when it is possible and either the
  * functions are evaluated in double precision, at most 60 % of the sites are prediction sites
  * and sites x chains <= 2^25, or at most 40 % are prediction sites and sites x chains <= 2^21

@@ -1189,7 +1189,7 @@ static int auto_path(const mpr_ctx* c)
     const double frac = (double)P / (double)N, work = (double)N * c->C;
     // the tiled path wins where the single-precision sweep is latency-bound (one launch per
     // sweep instead of two, no list reads): small grids with single-precision functions
-    if (tiled_possible(c) && c->fsingle && work <= 2097152.0) return MPR_SWEEP_TILED;
+    if (tiled_possible(c) && c->fsingle && work <= 1572864.0) return MPR_SWEEP_TILED;
     const bool prefer = c->fsingle ? (frac <= 0.4 && work <= 2097152.0)
                                    : (frac <= 0.6 && work <= 33554432.0);
     return (sparse_possible(c) && prefer) ? MPR_SWEEP_SPARSE : MPR_SWEEP_FUSED;
@@ -1458,7 +1458,7 @@ static void enqueue_tiled(mpr_ctx* c, int flags, int sweep_off, int src_buf, con
     a.g0 = c->gcs[0];
     a.inv_piq = 1.0 / (3.14159265358979323846 * c->cfg.q);
     const int waves = (c->sprec == MPR_FP16 || c->sprec == MPR_FIX16 || c->fsingle) ? tile_waves<float>()
-                                                                                     : tile_waves<double>();
+                                                                                     : tile_waves<double>();   // equal today
     hipLaunchKernelGGL(tiled_fn(c, flags), dim3((unsigned)c->n_tiles), dim3(kWave * waves), 0,
                        c->stream, a);
 }
