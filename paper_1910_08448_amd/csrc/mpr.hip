@@ -628,19 +628,21 @@ template <class S, class F> SparseFn pick_sparse(int flags, bool per, int colour
 
 using TiledFn = void (*)(TiledArgs);
 
-template <class S, class F, bool PER> TiledFn pick_tiled_b(int flags)
+template <class S, class F, bool PER, int NW> TiledFn pick_tiled_b(int flags)
 {
     switch (flags) {
-    case 0: return k_tiled<S, F, 0, PER>;
-    case F_ENERGY: return k_tiled<S, F, F_ENERGY, PER>;
-    case F_ACC: return k_tiled<S, F, F_ACC, PER>;
-    default: return k_tiled<S, F, F_DEC, PER>;
+    case 0: return k_tiled<S, F, 0, PER, NW>;
+    case F_ENERGY: return k_tiled<S, F, F_ENERGY, PER, NW>;
+    case F_ACC: return k_tiled<S, F, F_ACC, PER, NW>;
+    default: return k_tiled<S, F, F_DEC, PER, NW>;
     }
 }
 
-template <class S, class F> TiledFn pick_tiled(int flags, bool per)
+template <class S, class F> TiledFn pick_tiled(int flags, bool per, bool large)
 {
-    return per ? pick_tiled_b<S, F, true>(flags) : pick_tiled_b<S, F, false>(flags);
+    if (large)
+        return per ? pick_tiled_b<S, F, true, kTileWavesLarge>(flags) : pick_tiled_b<S, F, false, kTileWavesLarge>(flags);
+    return per ? pick_tiled_b<S, F, true, kTileWavesSmall>(flags) : pick_tiled_b<S, F, false, kTileWavesSmall>(flags);
 }
 
 }  // namespace
@@ -1415,14 +1417,21 @@ static SweepFn sweep_fn(const mpr_ctx* c, int flags)
     }
 }
 
+// four waves also with double-precision functions, whose registers leave three waves per SIMD
+static int tile_waves(const mpr_ctx* c)
+{
+    const bool fdouble = !c->fsingle && c->sprec != MPR_FP16 && c->sprec != MPR_FIX16;
+    return (c->n_tiles >= kTileWavesSwitch || fdouble) ? kTileWavesLarge : kTileWavesSmall;
+}
+
 static TiledFn tiled_fn(const mpr_ctx* c, int flags)
 {
-    const bool per = c->cfg.boundary == MPR_PERIODIC;
+    const bool per = c->cfg.boundary == MPR_PERIODIC, large = tile_waves(c) == kTileWavesLarge;
     switch (c->sprec) {
-    case MPR_FP64: return c->fsingle ? pick_tiled<double, float>(flags, per) : pick_tiled<double, double>(flags, per);
-    case MPR_FP32: return c->fsingle ? pick_tiled<float, float>(flags, per) : pick_tiled<float, double>(flags, per);
-    case MPR_FIX16: return pick_tiled<Fix15, float>(flags, per);
-    default: return pick_tiled<_Float16, float>(flags, per);
+    case MPR_FP64: return c->fsingle ? pick_tiled<double, float>(flags, per, large) : pick_tiled<double, double>(flags, per, large);
+    case MPR_FP32: return c->fsingle ? pick_tiled<float, float>(flags, per, large) : pick_tiled<float, double>(flags, per, large);
+    case MPR_FIX16: return pick_tiled<Fix15, float>(flags, per, large);
+    default: return pick_tiled<_Float16, float>(flags, per, large);
     }
 }
 
@@ -1457,8 +1466,7 @@ static void enqueue_tiled(mpr_ctx* c, int flags, int sweep_off, int src_buf, con
     a.ntx = c->tiles_ntx;
     a.g0 = c->gcs[0];
     a.inv_piq = 1.0 / (3.14159265358979323846 * c->cfg.q);
-    const int waves = (c->sprec == MPR_FP16 || c->sprec == MPR_FIX16 || c->fsingle) ? tile_waves<float>()
-                                                                                     : tile_waves<double>();   // equal today
+    const int waves = tile_waves(c);
     hipLaunchKernelGGL(tiled_fn(c, flags), dim3((unsigned)c->n_tiles), dim3(kWave * waves), 0,
                        c->stream, a);
 }

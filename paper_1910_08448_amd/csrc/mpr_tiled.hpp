@@ -23,10 +23,12 @@
 namespace mpr {
 
 constexpr int kTileCols = 64;                     // plane columns per tile (128 grid columns)
-// waves per block (one block per tile): with four, more blocks share a CU and overlap their
-// phases (measured against two, eight and sixteen: equal on 1024^2, 21 % faster on 16384^2
-// than eight)
-template <class F> constexpr int tile_waves() { return 4; }
+// waves per block (one block per tile), a template parameter of the kernel: eight while the
+// tiles fit the chip a few times over (a sweep is then bound by one block's latency, which
+// more waves shorten: 3 % faster whole steps on 1024^2), four for more tiles (more blocks per
+// CU overlap their phases: 21 % faster on 16384^2); two and sixteen were slower
+constexpr int kTileWavesSmall = 8, kTileWavesLarge = 4;
+constexpr int kTileWavesSwitch = 2048;             // tiles from which four waves are used
 
 // rows per tile: 16 when a staged element (raw value and its (cos, sin)) takes at most 12
 // bytes, else 8, which keeps a block's LDS at 30-45 KB
@@ -61,8 +63,8 @@ struct TiledArgs {
 
 template <class F> struct alignas(2 * sizeof(F)) CosSin { F c, s; };
 
-template <class S, class F, int FLAGS, bool PER>
-__global__ __launch_bounds__(tile_waves<F>() * kWave) void k_tiled(TiledArgs a)
+template <class S, class F, int FLAGS, bool PER, int NW>
+__global__ __launch_bounds__(NW * kWave) void k_tiled(TiledArgs a)
 {
     using St = Store<S>;
     using M = Math<F>;
@@ -72,7 +74,7 @@ __global__ __launch_bounds__(tile_waves<F>() * kWave) void k_tiled(TiledArgs a)
     constexpr int R1 = TY + 4, W1 = TX + 4;       // colour-1 stage: rows y0-2 ..., columns k0-2 ...
     constexpr int R0 = TY + 2, W0 = TX + 2;       // colour-0 stage: rows y0-1 ..., columns k0-1 ...
     constexpr int N1 = R1 * W1, N0 = R0 * W0;
-    constexpr int NW = tile_waves<F>(), NT = kWave * NW;
+    constexpr int NT = kWave * NW;
     // a stage is read in passes of one 64-column row segment per wave (rows wave, wave + NW, ...)
     // plus one pass over the columns past the first 64 (4 for colour 1, 2 for colour 0)
     constexpr int I1 = (R1 + NW - 1) / NW, I0 = (R0 + NW - 1) / NW;

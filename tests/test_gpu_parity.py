@@ -651,3 +651,23 @@ def test_autotuned_path_reproduces_the_chosen_path(mpr, precision):
     assert np.array_equal(tuned.predictions().cpu().numpy(), forced.predictions().cpu().numpy())
     again = _gpu_ctx(mpr, w["z"], w["mask"], tile_rows=-1, **kw)
     assert again.sweep_mode() == mode
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_tiled_four_wave_blocks_equal_sparse(mpr, precision):
+    """From 2048 tiles on, the tiled kernel runs four-wave blocks (eight below): on a
+    2048 x 2048 grid (2048 tiles) the run still equals the compacted path's bit for bit."""
+    H = W = 2048
+    rng = np.random.default_rng(12)
+    z = rng.normal(50.0, 10.0, (H, W))
+    mask = (rng.random((H, W)) >= 0.4).astype(np.uint8)
+    z = np.where(mask == 1, z, np.nan)
+    res = []
+    for mode in (mpr.SWEEP_SPARSE, mpr.SWEEP_TILED):
+        ctx = _gpu_ctx(mpr, z, mask, precision=precision, sweep_mode=mode, seed=17)
+        T = ctx.infer_temperature(12)
+        ctx.run(4)
+        res.append((T, ctx.trace(0), ctx.predictions().cpu().numpy()))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+    assert np.array_equal(res[0][2], res[1][2])
