@@ -17,6 +17,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -36,7 +37,7 @@ def _infer_sweep_kind(name):
     or None."""
     if "k_sweep" in name and ("1, false" in name or "Li1ELb0" in name):
         return "fused"
-    if "k_tiled" in name and (", 1, false>" in name or ", 1, true>" in name or
+    if "k_tiled" in name and (re.search(r"k_tiled<[^,<>]+, [^,<>]+, 1, (false|true)[,>]", name) or
                               "Li1ELb0E" in name or "Li1ELb1E" in name):
         return "tiled"
     if "k_sparse" in name:
