@@ -110,7 +110,7 @@ typedef struct mpr_config {
  * in single precision and sites x chains <= 1.5 * 2^20 (small grids, where a sweep is bound by
  * latency: one launch instead of two); otherwise SPARSE when it is possible and either the
  * functions are evaluated in double precision, at most 60 % of the sites are prediction sites
- * and sites x chains <= 2^25, or at most 40 % are prediction sites and sites x chains <= 2^21
+ * and sites x chains <= 2^25, or at most 40 % are prediction sites and sites x chains <= 2^23
  * (measured crossovers on MI355X); FUSED otherwise.  The choice depends on the loaded data and
  * configuration only (or, with tile_rows = -1, on the autotuner's timing) and is fixed for the
  * context until the next load. */
