@@ -517,9 +517,11 @@ def test_automatic_path_choice(mpr):
         ctx = _gpu_ctx(mpr, z, mask, precision=prec,
                        energy_prec=mpr.PREC_SINGLE if esingle else mpr.PREC_DEFAULT)
         assert ctx.sweep_mode() == want, (p, prec, esingle)
-    # past the tiled limit: compacted up to 2^23 sites with few prediction sites, else fused
+    # the tiled limit (1.5 * 2^20 sites x chains), then compacted up to 2^23 sites with few
+    # prediction sites, else fused
     rng = np.random.default_rng(3)
-    for side, p, want in [(1536, 0.33, mpr.SWEEP_SPARSE), (2896, 0.33, mpr.SWEEP_SPARSE),
+    for side, p, want in [(1254, 0.33, mpr.SWEEP_TILED), (1255, 0.33, mpr.SWEEP_SPARSE),
+                          (1536, 0.33, mpr.SWEEP_SPARSE), (2896, 0.33, mpr.SWEEP_SPARSE),
                           (2048, 0.5, mpr.SWEEP_FUSED), (4096, 0.33, mpr.SWEEP_FUSED)]:
         mask = (rng.random((side, side)) >= p).astype(np.uint8)
         z = np.where(mask == 1, rng.standard_normal((side, side)), np.nan)
