@@ -10,18 +10,15 @@ own Philox words.  The whole method then runs at full size and is checked agains
 hold at any size: sample sites reproduced exactly, predictions inside the sample range, the
 temperature inside its bounds, finite acceptance rates and errors.
 """
-import math
-
 import numpy as np
 import pytest
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-from oracle import oracle as O                      # noqa: E402
+from oracle_sites import oracle_sites              # noqa: E402
 from paper_1910_08448_amd import synth              # noqa: E402
 
-TWO_PI = 2.0 * math.pi
 T_SWEEP, ALPHA, SWEEP = 0.02, 0.3, 3
 STORE = {1: np.float32, 2: np.float16}               # storage precision -> numpy type
 
@@ -69,30 +66,6 @@ def _mapped_samples(g):
     return np.where(mask == 1, (np.nan_to_num(z) - lo) / (hi - lo), 0.0)
 
 
-def _oracle_sites(u, mask, sites, seed, chain_word):
-    """Decision bits and new angles (turns) of the sampled prediction sites after one sweep,
-    from the oracle's single-site update on a 5 x 5 neighbourhood (clipped at the open edges):
-    a colour-1 site sees its colour-0 neighbours' new angles, which the oracle computes first."""
-    H, W = mask.shape
-    dec = np.zeros(len(sites), np.uint8)
-    new = np.zeros(len(sites))
-    for k, (y, x) in enumerate(sites):
-        y0, y1, x0, x1 = max(0, y - 2), min(H, y + 3), max(0, x - 2), min(W, x + 3)
-        phi = np.ascontiguousarray(TWO_PI * u[y0:y1, x0:x1])
-        m = mask[y0:y1, x0:x1]
-        cy, cx = y - y0, x - x0
-        if (x + y) & 1:
-            for dy, dx in ((-1, 0), (1, 0), (0, -1), (0, 1)):
-                ny, nx = cy + dy, cx + dx
-                if 0 <= ny < phi.shape[0] and 0 <= nx < phi.shape[1] and not m[ny, nx]:
-                    wa, wb = O.site_words(seed, W, y + dy, x + dx, SWEEP, chain_word, 0)
-                    O.site_update(phi, ny, nx, T_SWEEP, ALPHA, wa, wb)
-        wa, wb = O.site_words(seed, W, y, x, SWEEP, chain_word, 0)
-        dec[k] = O.site_update(phi, cy, cx, T_SWEEP, ALPHA, wa, wb)
-        new[k] = phi[cy, cx] / TWO_PI
-    return dec, new
-
-
 CASES = [("grid4096", 2), ("batch256", 2), ("batch256", 1), ("grid16384", 2)]
 
 
@@ -127,7 +100,7 @@ def test_full_size_sampled_sites_and_run(mpr, name, precision):
         free = np.argwhere(g["mask"] == 0)
         for ch in range(chains):
             sites = [tuple(map(int, free[i])) for i in rng.choice(len(free), size=min(per_chain, len(free)), replace=False)]
-            do, uo = _oracle_sites(states[gi][ch], g["mask"], sites, seed, gi * chains + ch)
+            do, uo = oracle_sites(states[gi][ch], g["mask"], sites, seed, SWEEP, gi * chains + ch, T_SWEEP, ALPHA)
             base = offs[gi] + ch * H * W
             idx = np.array([base + y * W + x for y, x in sites])
             same = dg[idx] == do
