@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1981,7 +1982,13 @@ int mpr_bench_sweeps(mpr_ctx* c, int32_t n)
 // recomputes.  The sweep's results do not depend on the choice (tested bitwise), so the tuner
 // may pick any candidate; it times n inference sweeps per candidate from a saved state, restores
 // the state, and remembers the winner per shape signature (in memory, and in the text file named
-// by MPR_TUNE_CACHE if set).
+// by MPR_TUNE_CACHE if set).  The table is shared by every context of the process: callers hold
+// tune_mutex() while they use it.
+static std::mutex& tune_mutex()
+{
+    static std::mutex m;
+    return m;
+}
 static std::map<std::string, int>& tune_cache()
 {
     static std::map<std::string, int> m;
@@ -2044,7 +2051,6 @@ static int autotune(mpr_ctx* c, int n, int* best_out)
         return MPR_OK;
     }
     const std::string key = tune_key(c);
-    auto& cache = tune_cache();
     auto finish = [&](int path, int rows) -> int {
         int rc = MPR_OK;
         if (path == MPR_SWEEP_FUSED && rows != c->rows) rc = use_rows(c, rows);
@@ -2052,8 +2058,14 @@ static int autotune(mpr_ctx* c, int n, int* best_out)
         if (best_out) *best_out = c->rows;
         return rc;
     };
-    auto hit = cache.find(key);
-    if (hit != cache.end()) return finish(hit->second / 1000, hit->second % 1000);
+    int cached = -1;
+    {
+        std::lock_guard<std::mutex> lock(tune_mutex());
+        auto& cache = tune_cache();
+        auto hit = cache.find(key);
+        if (hit != cache.end()) cached = hit->second;
+    }
+    if (cached >= 0) return finish(cached / 1000, cached % 1000);
 
     int maxH = 0;
     for (int g = 0; g < c->G; ++g) maxH = std::max<int>(maxH, (int)c->H[g]);
@@ -2111,9 +2123,13 @@ static int autotune(mpr_ctx* c, int n, int* best_out)
     (void)hipEventDestroy(e1);
     (void)hipFree(saved);
     if (rc) return rc;
-    cache[key] = best_path * 1000 + best_rows;
-    if (const char* path = std::getenv("MPR_TUNE_CACHE")) {
-        if (FILE* f = std::fopen(path, "a")) { std::fprintf(f, "%s %d\n", key.c_str(), cache[key]); std::fclose(f); }
+    {
+        std::lock_guard<std::mutex> lock(tune_mutex());
+        auto& cache = tune_cache();
+        cache[key] = best_path * 1000 + best_rows;
+        if (const char* path = std::getenv("MPR_TUNE_CACHE")) {
+            if (FILE* f = std::fopen(path, "a")) { std::fprintf(f, "%s %d\n", key.c_str(), cache[key]); std::fclose(f); }
+        }
     }
     return finish(best_path, best_rows);
 }

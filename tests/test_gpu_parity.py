@@ -680,3 +680,31 @@ def test_tiled_four_wave_blocks_equal_sparse(mpr, precision):
     assert np.array_equal(res[0][0], res[1][0])
     assert np.array_equal(res[0][1], res[1][1])
     assert np.array_equal(res[0][2], res[1][2])
+
+
+def test_contexts_on_two_host_threads(mpr):
+    """Two contexts driven from two host threads at once, both autotuning at load (the tuner's
+    table is shared by the process), give the results each gives alone."""
+    import threading
+    fields = [_field(52, 76, 5), _field(44, 90, 6)]      # shapes no other test tunes
+
+    def run(i, out):
+        truth, z, mask = fields[i]
+        ctx = _gpu_ctx(mpr, z, mask, precision=mpr.FP32, sweep_mode=mpr.SWEEP_FUSED, tile_rows=-1,
+                       seed=9 + i)
+        ctx.infer_temperature(20)
+        ctx.run(5)
+        out[i] = ctx.predictions().cpu().numpy()
+
+    both = [None, None]
+    threads = [threading.Thread(target=run, args=(i, both)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in threads)
+    alone = [None, None]
+    for i in range(2):
+        run(i, alone)
+    for i in range(2):
+        assert both[i] is not None and np.array_equal(both[i], alone[i])
