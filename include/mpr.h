@@ -100,9 +100,12 @@ typedef struct mpr_config {
  * SPARSE: two launches per sweep (one per colour) over lists of the prediction sites only, built
  *   at load; needs double-precision energy and grids with H < 65536 and
  *   ceil(ceil(W / 2) / 2) * 2 < 65536.
- * TILED: one launch per sweep, one block per tile of 8 or 16 rows x 128 columns staged in LDS
- *   with its halo; each colour's prediction sites are compacted into a list inside the block,
- *   and the colour-0 sites around the tile are recomputed; needs double-precision energy.
+ * TILED: one launch per sweep, one block per tile of 128 columns staged in LDS with its halo
+ *   (eight-wave blocks on tiles of 32 rows, 16 with 8-byte spins, while the grids hold fewer
+ *   than 2048 tiles of half that height; otherwise four-wave blocks on tiles of 16 or 8 rows,
+ *   also with double-precision functions); each colour's prediction sites are compacted into
+ *   a list inside the block, and the colour-0 sites around the tile are recomputed; needs
+ *   double-precision energy.
  * All three take identical decisions from identical states; SPARSE and TILED also sum the
  * energy identically (bitwise equal results), while FUSED groups the bonds differently, so its
  * temperature trajectories agree with theirs to rounding, not bitwise.

@@ -714,6 +714,7 @@ struct mpr_ctx {
     int4* d_tiles = nullptr;
     int64_t tiles_cap = 0;
     int32_t n_tiles = 0, tiles_ntx = 0;
+    bool tiles_big = false;     // eight-wave blocks on tiles of twice the base height
 };
 
 static const char* kStatusText[] = {
@@ -1032,11 +1033,17 @@ template <class S, class F> static void launch_econst(mpr_ctx* c)
 
 static int build_econst(mpr_ctx* c);
 
-// tiles of the tiled path: per (grid, chain), row blocks of tile_rows x column blocks of
-// kTileCols plane columns, row-major (neighbouring tiles get neighbouring block numbers)
+// tiles of the tiled path: per (grid, chain), row blocks of the tile height x column blocks of
+// kTileCols plane columns, row-major (neighbouring tiles get neighbouring block numbers).  With
+// single-precision functions and fewer than kTileWavesSwitch tiles of the base height, the
+// eight-wave blocks and their tiles of twice that height; else four-wave blocks.
 template <class S, class F> static int build_tiles_t(mpr_ctx* c)
 {
-    constexpr int TY = tile_rows<S, F>();
+    int64_t base = 0;
+    for (const GcDesc& d : c->gcs)
+        base += (int64_t)((d.H + tile_rows<S, F>() - 1) / tile_rows<S, F>()) * ((d.wc + kTileCols - 1) / kTileCols);
+    c->tiles_big = sizeof(F) == 4 && base < kTileWavesSwitch;
+    const int TY = c->tiles_big ? tile_rows_for<S, F, kTileWavesSmall>() : tile_rows_for<S, F, kTileWavesLarge>();
     std::vector<int4> t;
     for (int i = 0; i < (int)c->gcs.size(); ++i) {
         const GcDesc& d = c->gcs[i];
@@ -1418,11 +1425,11 @@ static SweepFn sweep_fn(const mpr_ctx* c, int flags)
     }
 }
 
-// four waves also with double-precision functions, whose registers leave three waves per SIMD
+// the tiles built for the loaded data fix the block (four waves also with double-precision
+// functions, whose registers leave three waves per SIMD)
 static int tile_waves(const mpr_ctx* c)
 {
-    const bool fdouble = !c->fsingle && c->sprec != MPR_FP16 && c->sprec != MPR_FIX16;
-    return (c->n_tiles >= kTileWavesSwitch || fdouble) ? kTileWavesLarge : kTileWavesSmall;
+    return c->tiles_big ? kTileWavesSmall : kTileWavesLarge;
 }
 
 static TiledFn tiled_fn(const mpr_ctx* c, int flags)
