@@ -109,12 +109,13 @@ typedef struct mpr_config {
  * All three take identical decisions from identical states; SPARSE and TILED also sum the
  * energy identically (bitwise equal results), while FUSED groups the bonds differently, so its
  * temperature trajectories agree with theirs to rounding, not bitwise.
- * AUTO picks TILED when the energy is summed in double precision, the functions are evaluated
- * in single precision and sites x chains <= 1.5 * 2^20 (small grids, where a sweep is bound by
- * latency: one launch instead of two); otherwise SPARSE when it is possible and either the
- * functions are evaluated in double precision, at most 60 % of the sites are prediction sites
- * and sites x chains <= 2^25, or at most 40 % are prediction sites and sites x chains <= 2^23
- * (measured crossovers on MI355X); FUSED otherwise.  The choice depends on the loaded data and
+ * AUTO picks TILED when the energy is summed in double precision, sites x chains <= 1.5 * 2^20
+ * (small grids, where a sweep is bound by latency: one launch instead of two) and either the
+ * functions are evaluated in single precision or more than 60 % of the sites are prediction
+ * sites; otherwise SPARSE when it is possible and either the functions are evaluated in double
+ * precision with at most 60 % prediction sites and sites x chains <= 2^25 or at most 70 % and
+ * sites x chains <= 2^23, or in single precision with at most 40 % prediction sites and
+ * sites x chains <= 2^23 (measured crossovers on MI355X); FUSED otherwise.  The choice depends on the loaded data and
  * configuration only (or, with tile_rows = -1, on the autotuner's timing) and is fixed for the
  * context until the next load. */
 typedef enum mpr_sweep_mode {

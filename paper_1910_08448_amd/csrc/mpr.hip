@@ -1197,11 +1197,12 @@ static int auto_path(const mpr_ctx* c)
         N += c->H[g] * c->W[g];
     }
     const double frac = (double)P / (double)N, work = (double)N * c->C;
-    // the tiled path wins where the single-precision sweep is latency-bound (one launch per
-    // sweep instead of two, no list reads): small grids with single-precision functions
-    if (tiled_possible(c) && c->fsingle && work <= 1572864.0) return MPR_SWEEP_TILED;
+    // the tiled path wins where a sweep is latency-bound (one launch per sweep instead of two,
+    // no list reads): small grids with single-precision functions, and with double-precision
+    // functions once most sites are prediction sites
+    if (tiled_possible(c) && work <= 1572864.0 && (c->fsingle || frac > 0.6)) return MPR_SWEEP_TILED;
     const bool prefer = c->fsingle ? (frac <= 0.4 && work <= 8388608.0)
-                                   : (frac <= 0.6 && work <= 33554432.0);
+                                   : ((frac <= 0.6 && work <= 33554432.0) || (frac <= 0.7 && work <= 8388608.0));
     return (sparse_possible(c) && prefer) ? MPR_SWEEP_SPARSE : MPR_SWEEP_FUSED;
 }
 

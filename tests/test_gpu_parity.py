@@ -505,13 +505,14 @@ def test_sparse_batch_equals_single_grids(mpr, mode):
 
 
 def test_automatic_path_choice(mpr):
-    """AUTO takes the tiled path for small grids with single-precision functions, the compacted
-    path for small grids with few prediction sites and double-precision functions, when the
-    energy is summed in double precision; the fused path otherwise."""
+    """AUTO takes the tiled path for small grids with single-precision functions or with
+    double-precision functions and mostly prediction sites, the compacted path for small grids
+    with fewer prediction sites and double-precision functions, when the energy is summed in
+    double precision; the fused path otherwise."""
     for p, prec, esingle, want in [(0.33, mpr.FP32, False, mpr.SWEEP_TILED),
                                    (0.5, mpr.FP16, False, mpr.SWEEP_TILED),
                                    (0.5, mpr.FP64, False, mpr.SWEEP_SPARSE),
-                                   (0.9, mpr.FP64, False, mpr.SWEEP_FUSED),
+                                   (0.9, mpr.FP64, False, mpr.SWEEP_TILED),
                                    (0.33, mpr.FP32, True, mpr.SWEEP_FUSED)]:
         truth, z, mask = _field(64, 64, 5, p=p)
         ctx = _gpu_ctx(mpr, z, mask, precision=prec,
@@ -526,6 +527,13 @@ def test_automatic_path_choice(mpr):
         mask = (rng.random((side, side)) >= p).astype(np.uint8)
         z = np.where(mask == 1, rng.standard_normal((side, side)), np.nan)
         assert _gpu_ctx(mpr, z, mask, precision=mpr.FP32).sweep_mode() == want, (side, p)
+    # double-precision functions past the tiled limit: compacted up to 70 % prediction sites and
+    # 2^23 sites, else fused
+    for side, p, want in [(2048, 0.66, mpr.SWEEP_SPARSE), (2048, 0.9, mpr.SWEEP_FUSED),
+                          (4096, 0.66, mpr.SWEEP_FUSED)]:
+        mask = (rng.random((side, side)) >= p).astype(np.uint8)
+        z = np.where(mask == 1, rng.standard_normal((side, side)), np.nan)
+        assert _gpu_ctx(mpr, z, mask, precision=mpr.FP64).sweep_mode() == want, (side, p)
     truth, z, mask = _field(64, 64, 5)
     for mode in (mpr.SWEEP_SPARSE, mpr.SWEEP_TILED):
         with pytest.raises(mpr.MprError):
