@@ -102,8 +102,8 @@ typedef struct mpr_config {
  *   ceil(ceil(W / 2) / 2) * 2 < 65536.
  * TILED: one launch per sweep, one block per tile of 128 columns staged in LDS with its halo
  *   (eight-wave blocks on tiles of 32 rows, 16 with 8-byte spins, while the grids hold fewer
- *   than 2048 tiles of half that height; otherwise four-wave blocks on tiles of 16 or 8 rows,
- *   also with double-precision functions); each colour's prediction sites are compacted into
+ *   than 2048 tiles of half that height; otherwise four-wave blocks on tiles of 16 rows, 8 with
+ *   8-byte spins, and with double-precision functions four-wave blocks on 16-row tiles); each colour's prediction sites are compacted into
  *   a list inside the block, and the colour-0 sites around the tile are recomputed; needs
  *   double-precision energy.
  * All three take identical decisions from identical states; SPARSE and TILED also sum the

@@ -31,10 +31,12 @@ constexpr int kTileWavesSmall = 8, kTileWavesLarge = 4;
 constexpr int kTileWavesSwitch = 2048;             // tiles (of the base height) from which four waves are used
 
 // base rows per tile: 16 when a staged element (raw value and its (cos, sin)) takes at most 12
-// bytes, else 8, which keeps a four-wave block's LDS at 28-42 KB
+// bytes or the functions are evaluated in double precision, else 8.  Four-wave blocks then take
+// 28-67 KB of LDS; with double-precision functions their registers allow three waves per SIMD
+// anyway, and 16-row tiles halve the staged halo (11 % faster kernels on 1024^2)
 template <class S, class F> constexpr int tile_rows()
 {
-    return (sizeof(typename Store<S>::raw) + 2 * sizeof(F) <= 12) ? 16 : 8;
+    return (sizeof(typename Store<S>::raw) + 2 * sizeof(F) <= 12 || sizeof(F) == 8) ? 16 : 8;
 }
 // rows per tile of a block of NW waves: eight-wave blocks take tiles of twice the base height
 // (49-69 KB of LDS, two or three blocks per CU): on a grid that fits the chip in one round, fewer and
