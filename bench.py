@@ -6,16 +6,24 @@ HBM: load (validation, data map, sample energy, initial state), temperature infe
 second over the whole step: one site update = one hybrid (over-relaxation + Metropolis) update
 of one prediction site in one sweep of one chain.
 
+The default workload is the batch of 256 grids (sides 64 ... 1024, four chains each) with FP32
+angle storage and FP32 functions: the reduced-precision batched path.
+
 Also printed in the same JSON line:
-  roofline      the sweep kernel against the vector-ALU roof it is bound by: the method's
-                arithmetic per site update (OPS_PER_UPDATE FP32-rate issue slots, see below)
-                times the site updates of one launch, over the kernel's average launch time
-                (HIP events on the library's stream); its algorithmic HBM bytes ((N + 2P) s per
-                chain, s = bytes per angle) against the 8 TB/s HBM roof are reported beside it,
-                and `traffic` is the HBM bytes per launch that rocprofv3 counted for the same
-                kernel source (null when the kernel changed since the counters were taken)
-  cpu_baseline  the FP64 CPU oracle timed on a bounded sample of the same workload
-  setups        the same measurements for the other precision setups / workloads
+  roofline      the inference sweep kernel (its average launch time from HIP events on the
+                library's stream over the timed steps) against the vector-ALU roof that bounds
+                it: the method's VALU issue units per site update (OPS_PER_UPDATE) times the
+                site updates of one launch, over the launch time, against two VALU
+                instructions per quad-cycle per SIMD; beside it (`hbm`) the algorithmic HBM
+                bytes of one launch ((N + 2P) s per chain, s = bytes per angle) against the
+                8 TB/s HBM roof and against a measured device copy, and `traffic`, the HBM
+                bytes per launch rocprofv3 counted for the same kernel source (null when the
+                kernel changed since the counters were taken)
+  cpu_baseline  the FP64 CPU oracle timed on a bounded sample of the same workload, on every
+                host core and on one
+  setups        the same measurements for the other precision setups / workloads, and
+                `fp64_factor`: the primary setup's rate over the FP64 setup's on the same
+                workload
 """
 import argparse
 import json
@@ -31,15 +39,18 @@ sys.path.insert(0, ROOT)
 from paper_1910_08448_amd import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# FP32 vector issue slots per second: 157.3 TFLOP/s counts a fused multiply-add as 2 flops
-ALU_PEAK_TOPS = 157.3 / 2
-# The method's arithmetic per site update, in FP32-rate issue slots (a transcendental and a
-# 32 x 32 -> 64-bit multiply count 4, at a quarter of the rate): field sums 6, over-relaxation
-# (atan2 16, reflection and range test 5) 21, (cos, sin) of the current angle 9, half a
-# Philox4x32-10 call (10 rounds of two 4-slot multiplies and two xors) 50, Metropolis (two
-# uniforms, proposal and range test, its (cos, sin), the energy change, exp, accept and
-# select) 30, energy and acceptance sums 3.
-OPS_PER_UPDATE = 119
+# VALU issue roof, in lane-operations per second: 256 CUs x 4 SIMDs x 64 lanes x 2.4 GHz / 4
+# cycles per wave64 instruction = 39.3 T at one instruction per quad-cycle; gfx950 issues a
+# second VALU instruction in the same quad-cycle for some instruction pairs (counter
+# SQ_ACTIVE_INST_VALU2), so two per quad-cycle, 78.6 T, is the roof (the published 157.3
+# TFLOP/s FP32 figure with an FMA counted as two operations)
+ALU_PEAK_TOPS = 256 * 4 * 64 * 2.4e9 / 4 * 2 / 1e12
+ALU_SINGLE_ISSUE_TOPS = ALU_PEAK_TOPS / 2
+# The method's arithmetic per site update in VALU issue units (transcendentals count two, as in
+# SQ_ACTIVE_INST_VALU): the compiled single-precision site code -- field sums of four
+# neighbours, half a Philox4x32-10 call, the hybrid update (atan2, two sin/cos pairs, exp,
+# uniforms, tests and selects) and the fixed-point energy term -- issues about 110 per update
+OPS_PER_UPDATE = 110
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 PREC = {"fp64": 0, "fp32": 1, "fp16": 2, "fix16": 3}
 BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "fix16": 2}
@@ -47,8 +58,12 @@ DTYPE = {"fp64": "f64", "fp32": "f32", "fp16": "f32", "fix16": "f32"}   # arithm
 SWEEPS = {"grid64": (256, 100), "grid1024": (1000, 100), "grid4096": (1000, 100),
           "grid16384": (500, 50), "batch256": (1000, 100)}
 CHAINS = {"batch256": 4}
+# secondary setups of a default run (besides the primary workload's other precisions), and the
+# larger single grids of --extended
+SETUPS = [("grid1024", "fp32")]
 EXTENDED = [("grid4096", "fp16"), ("grid16384", "fp16"), ("grid16384", "fp32"),
-            ("grid16384", "fp64"), ("batch256", "fp16"), ("batch256", "fp32")]
+            ("grid16384", "fp64")]
+T_MIN, T_MAX = 1e-6, 10.0            # the library's default temperature clamp
 
 
 def kernel_source_sha():
@@ -108,12 +123,32 @@ class Inputs:
         self.n_pred = [int((g["mask"] == 0).sum()) for g in self.grids]
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
 def oracle_reference(name, p_missing):
-    path = os.path.join(ROOT, "tests", "golden", "oracle_reference.json")
-    if name != "grid1024" or not os.path.exists(path):
+    """The oracle's stored run of this workload (tests/golden, written by a script that calls
+    only the oracle), or None."""
+    key = {"grid1024": "grid1024_p%.2f" % (0.33 if p_missing is None else p_missing),
+           "grid4096": "grid4096", "grid16384": "grid16384",
+           "batch256": "batch256_sub16"}.get(name)
+    if key is None or (p_missing is not None and name != "grid1024"):
         return None
-    key = "grid1024_p%.2f" % (0.33 if p_missing is None else p_missing)
-    return json.load(open(path)).get(key)
+    path = os.path.join(GOLDEN, "oracle_reference.json")
+    try:
+        return json.load(open(path)).get(key)
+    except (OSError, ValueError):
+        return None
+
+
+def oracle_subset(name):
+    """Grids of the batch the oracle's stored run covers (all grids of a single-grid workload)."""
+    if name != "batch256":
+        return None
+    try:
+        return json.load(open(os.path.join(GOLDEN, "oracle_zhat_batch256_sub16.json")))["grids"]
+    except (OSError, ValueError, KeyError):
+        return None
 
 
 SWEEP_MODE = {"auto": 0, "fused": 1, "sparse": 2, "tiled": 3}
@@ -161,15 +196,26 @@ def measure(inp, precision, steps, warmup, kernel_launches, torch, M, sweep_mode
     log("%d steps of %s/%s: %.3f ms/step, %.4g site-updates/s"
         % (steps, inp.name, precision, ms_per_step, value))
 
+    # prediction error against the synthetic truth, over every grid and over the grids of the
+    # oracle's stored run (the paper's Delta MAAE: MAE relative to the FP64 oracle's, Sec. 3)
     zh = zhat.cpu().numpy()
-    errs, off = [], 0
-    for g, n in zip(inp.grids, inp.n_sites):
+    sub = oracle_subset(inp.name)
+    sub = set(sub) if sub is not None else None
+    abs_all, sq_all, n_all, abs_sub, n_sub, off = 0.0, 0.0, 0, 0.0, 0, 0
+    for gi, (g, n) in enumerate(zip(inp.grids, inp.n_sites)):
         m = (g["mask"] == 0).ravel()
-        errs.append(zh[off:off + n][m] - g["truth"].ravel()[m])
+        err = zh[off:off + n][m] - g["truth"].ravel()[m]
         off += n
-    err = np.concatenate(errs)
-    mae, rmse = float(np.abs(err).mean()), float(np.sqrt((err ** 2).mean()))
-    T_hat = [s["T"] for s in ctx.stats()]
+        abs_all += float(np.abs(err).sum())
+        sq_all += float((err ** 2).sum())
+        n_all += err.size
+        if sub is None or gi in sub:
+            abs_sub += float(np.abs(err).sum())
+            n_sub += err.size
+    mae, rmse = abs_all / n_all, float(np.sqrt(sq_all / n_all))
+    stats = ctx.stats()
+    T_hat = [s["T"] for s in stats]
+    clamped = sum(1 for t in T_hat if t <= T_MIN * (1 + 1e-12) or t >= T_MAX * (1 - 1e-12))
 
     # per inference sweep over the timed region (graph-captured launches, in-sweep control)
     kernel_ms = sum(a.elapsed_time(b) for a, b in marks) / (len(marks) * n_equil) if marks else None
@@ -193,9 +239,10 @@ def measure(inp, precision, steps, warmup, kernel_launches, torch, M, sweep_mode
     gbs = alg_bytes / (kernel_ms * 1e-3) / 1e9
     ops = OPS_PER_UPDATE * P
     tops = ops / (kernel_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(tops, 3), "peak": ALU_PEAK_TOPS,
-                "unit": "TOP/s", "frac": round(tops / ALU_PEAK_TOPS, 4),
+    roofline = {"bound": "alu", "achieved": round(tops, 3), "peak": round(ALU_PEAK_TOPS, 2),
+                "unit": "T VALU lane-ops/s", "frac": round(tops / ALU_PEAK_TOPS, 4),
                 "traffic": measured_traffic(inp.name, precision),
+                "frac_single_issue": round(tops / ALU_SINGLE_ISSUE_TOPS, 4),
                 "kernel": kernel_name, "kernel_ms": round(kernel_ms, 5),
                 "kernel_ms_back_to_back": round(kernel_ms_b2b, 5),
                 "ops_per_launch": ops, "ops_per_site_update": OPS_PER_UPDATE,
@@ -208,11 +255,12 @@ def measure(inp, precision, steps, warmup, kernel_launches, torch, M, sweep_mode
            "grids": len(inp.shapes), "sites": sum(inp.n_sites), "prediction_sites": sum(inp.n_pred),
            "chains": chains, "sweep_path": path, "n_equil": n_equil, "n_avg": n_avg,
            "lattice_site_rate": lattice_rate, "mae": mae, "rmse": rmse,
-           "T_hat": T_hat[:4], "roofline": roofline}
+           "T_hat": T_hat[:4], "T_hat_clamped": clamped, "roofline": roofline}
     ref = oracle_reference(inp.name, inp.p_missing)
     if ref is not None and chains == ref["chains"]:
         out["oracle_mae"] = ref["mae"]
-        out["mae_vs_oracle"] = mae / ref["mae"] - 1.0
+        out["mae_oracle_grids"] = abs_sub / n_sub
+        out["mae_vs_oracle"] = (abs_sub / n_sub) / ref["mae"] - 1.0
     return out
 
 
@@ -235,37 +283,58 @@ def streaming_copy_gbs(torch, mib=1024, reps=5):
     return gbs
 
 
-def cpu_baseline(grid, seed, seconds):
-    """The FP64 oracle on the host cores: inference sweeps of the same grid, as many as fit in
-    about `seconds` (calibrated on 3 sweeps)."""
+def _oracle_rate(O, grid, seed, chains, grid_id, threads, seconds):
+    """Inference sweeps of the oracle on one grid: as many as fit in about `seconds` (calibrated
+    on 2 sweeps); returns (site-updates/s, sweeps)."""
+    n_pred = int((grid["mask"] == 0).sum())
+    o = O.Oracle(seed=seed, n_chains=chains, grid_id=grid_id, n_threads=threads)
+    o.load(grid["z"], grid["mask"])
+    t = time.perf_counter()
+    o.infer_temperature(2)
+    per = (time.perf_counter() - t) / 2
+    o.close()
+    n = int(max(2, min(2000, seconds / max(per, 1e-9))))
+    o = O.Oracle(seed=seed, n_chains=chains, grid_id=grid_id, n_threads=threads)
+    o.load(grid["z"], grid["mask"])
+    t = time.perf_counter()
+    o.infer_temperature(n)
+    dt = time.perf_counter() - t
+    o.close()
+    return n_pred * chains * n / dt, n
+
+
+def cpu_baseline(inp, seconds):
+    """The FP64 oracle on the host: the first inference sweeps of one grid of the workload with
+    the workload's chains (for the batch, its grid whose side is nearest 512, with the batch's
+    Philox chain words), timed on every core the process may use and on one core."""
     from oracle import oracle as O
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
-        cores = os.cpu_count()
-    cores = max(1, min(cores, 16))
-    n_pred = int((grid["mask"] == 0).sum())
-    o = O.Oracle(seed=seed, n_threads=cores)
-    o.load(grid["z"], grid["mask"])
-    t = time.perf_counter()
-    o.infer_temperature(3)
-    per = (time.perf_counter() - t) / 3
-    n = int(max(3, min(2000, seconds / max(per, 1e-9))))
-    o2 = O.Oracle(seed=seed, n_threads=cores)
-    o2.load(grid["z"], grid["mask"])
-    t = time.perf_counter()
-    o2.infer_temperature(n)
-    dt = time.perf_counter() - t
+        cores = os.cpu_count() or 1
+    chains = CHAINS.get(inp.name, 1)
+    if inp.name == "batch256":
+        gi = int(np.argmin([abs(g["mask"].shape[0] - 512) for g in inp.grids]))
+    else:
+        gi = 0
+    grid = inp.grids[gi]
+    rate, n = _oracle_rate(O, grid, inp.mc_seed, chains, gi, cores, seconds)
+    rate1, n1 = _oracle_rate(O, grid, inp.mc_seed, chains, gi, 1, seconds)
     model = None
     try:
         with open("/proc/cpuinfo") as f:
             model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
     except OSError:
         pass
-    return {"value": n_pred * n / dt, "unit": "site-updates/s", "cores": cores, "kind": "oracle",
-            "cpu_model": model,
-            "sample": "first %d inference sweeps of grid 0 (%dx%d, %d prediction sites), 1 chain, FP64"
-                      % (n, grid["z"].shape[0], grid["z"].shape[1], n_pred)}
+    H, W = grid["mask"].shape
+    what = "grid %d of the workload (%dx%d, %d prediction sites), %d chain(s), FP64" % (
+        gi, H, W, int((grid["mask"] == 0).sum()), chains)
+    log("oracle: %.3g site-updates/s on %d cores, %.3g on one" % (rate, cores, rate1))
+    return {"value": rate, "unit": "site-updates/s", "cores": cores, "kind": "oracle",
+            "nproc": os.cpu_count(), "cpu_model": model,
+            "sample": "first %d inference sweeps of %s" % (n, what),
+            "single_thread": {"value": rate1, "cores": 1,
+                              "sample": "first %d inference sweeps of %s" % (n1, what)}}
 
 
 def main():
@@ -273,17 +342,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="grid1024", choices=sorted(SWEEPS))
+    ap.add_argument("--workload", default="batch256", choices=sorted(SWEEPS))
     ap.add_argument("--precision", default="fp32", choices=sorted(PREC))
     ap.add_argument("--p-missing", type=float, default=None)
     ap.add_argument("--sweep-mode", default="auto", choices=sorted(SWEEP_MODE),
                     help="sweep path: automatic choice, fused row blocks, compacted site lists, or LDS tiles")
     ap.add_argument("--kernel-launches", type=int, default=20)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--setup-steps", type=int, default=3, help="timed steps of each secondary setup")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="oracle time per CPU-baseline run (all cores, then one core)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-setups", action="store_true", help="only the primary setup")
     ap.add_argument("--extended", action="store_true",
-                    help="also the 4096^2, 16384^2 and 256-grid batched workloads")
+                    help="also the 4096^2 and 16384^2 single-grid workloads")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="copy a buffer of this many MiB once (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -313,7 +384,8 @@ def main():
 
     setups = []
     if not args.no_setups:
-        todo = [(args.workload, p) for p in ("fp64", "fp32", "fp16") if p != args.precision]
+        todo = [(args.workload, p) for p in ("fp16", "fp32", "fp64") if p != args.precision]
+        todo += [t for t in SETUPS if t[0] != args.workload]
         if args.extended:
             todo += EXTENDED
         for wl, prec in todo:
@@ -323,15 +395,15 @@ def main():
                         del inputs[k]
                 torch.cuda.empty_cache()
                 inputs[wl] = Inputs(wl, None, torch)
-            steps = max(1, min(args.steps, 3)) if wl != args.workload else args.steps
+            steps = max(1, min(args.steps, args.setup_steps))
             setups.append(measure(inputs[wl], prec, steps, 1, args.kernel_launches, torch, M,
                                   args.sweep_mode))
 
     cpu = None
     if not args.no_cpu_baseline:
-        g0 = inputs[args.workload].grids[0]
-        cpu = cpu_baseline(g0, inputs[args.workload].mc_seed, args.cpu_seconds)
+        cpu = cpu_baseline(inputs[args.workload], args.cpu_seconds)
 
+    fp64 = next((u for u in setups if u["workload"] == args.workload and u["precision"] == "fp64"), None)
     out = {
         "metric": "site-updates/s per precision setup (FP64/FP32/FP16) and prediction MAE vs FP64",
         "value": prim["value"], "unit": "site-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -343,12 +415,14 @@ def main():
                    "prediction_sites": prim["prediction_sites"], "chains": prim["chains"],
                    "n_equil": prim["n_equil"], "n_avg": prim["n_avg"],
                    "sweep_path": prim["sweep_path"]},
+        "fp64_factor": (prim["value"] / fp64["value"]) if fp64 else None,
         "mae": prim["mae"], "rmse": prim["rmse"], "T_hat": prim["T_hat"],
+        "T_hat_clamped": prim["T_hat_clamped"],
         "roofline": prim["roofline"],
         "cpu_baseline": cpu,
         "setups": setups,
     }
-    for k in ("oracle_mae", "mae_vs_oracle", "lattice_site_rate"):
+    for k in ("oracle_mae", "mae_oracle_grids", "mae_vs_oracle", "lattice_site_rate"):
         if k in prim:
             out[k] = prim[k]
     # the second HBM denominator: what a plain device-to-device copy achieves on this GPU

@@ -121,10 +121,15 @@ __global__ __launch_bounds__(256) void k_sample_energy(GridInfo* gi, const doubl
     const int64_t H = G.H, W = G.W, n = H * W;
     const double lo = G.zmin, inv = 1.0 / (G.zmax - G.zmin);
     int64_t e_hi = 0, e_lo = 0, cnt = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    // grid-stride loop with the site's (y, x) stepped along (one division per thread, not per
+    // site)
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t dy = stride / W, dx = stride - dy * W;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t y = i / W, x = i - y * W;
+    for (; i < n; i += stride, x += dx, y += dy) {
+        if (x >= W) { x -= W; ++y; }
         if (mask[G.site_off + i] != 1) continue;
-        const int64_t y = i / W, x = i - y * W;
         const double ui = (z[G.site_off + i] - lo) * inv;
         int64_t nb[2];
         nb[0] = (x + 1 < W) ? i + 1 : (periodic ? y * W : -1);
@@ -166,12 +171,17 @@ __global__ __launch_bounds__(256) void k_map_init(const GcDesc* gcs, const GridI
     const GridInfo& G = gi[g.grid];
     const int64_t per_plane = (int64_t)g.H * g.pitch;
     const double lo = G.zmin, inv = 1.0 / (G.zmax - G.zmin);
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < 2 * per_plane;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(e / per_plane);
-        const int64_t r = e - c * per_plane;
-        const int y = (int)(r / g.pitch);
-        const int k = (int)(r - (int64_t)y * g.pitch);
+    // element e = R pitch + k of the planes' 2 H rows (R = c H + y), stepped along the
+    // grid-stride loop without a division per element
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t dR = stride / g.pitch, dk = stride - dR * g.pitch;
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t R = e / g.pitch, kk = e - R * g.pitch;
+    for (; e < 2 * per_plane; e += stride, kk += dk, R += dR) {
+        if (kk >= g.pitch) { kk -= g.pitch; ++R; }
+        const int c = R >= g.H ? 1 : 0;
+        const int y = (int)(R - (int64_t)c * g.H);
+        const int k = (int)kk;
         const int x = 2 * k + ((y + c) & 1);
         typename St::raw v = 0;
         if (x < g.W) {
@@ -2073,7 +2083,16 @@ static int autotune(mpr_ctx* c, int n, int* best_out)
         auto hit = cache.find(key);
         if (hit != cache.end()) cached = hit->second;
     }
-    if (cached >= 0) return finish(cached / 1000, cached % 1000);
+    // a remembered winner (possibly read from a file) is used only if it names a path this
+    // context can run and one of the candidate row counts; otherwise the tuner times again
+    if (cached >= 0) {
+        const int path = cached / 1000, rows = cached % 1000;
+        const bool path_ok = path == MPR_SWEEP_FUSED || (path == MPR_SWEEP_SPARSE && sparse_possible(c)) ||
+                             (path == MPR_SWEEP_TILED && tiled_possible(c));
+        const bool rows_ok = std::find(std::begin(kRowCandidates), std::end(kRowCandidates), rows) !=
+                             std::end(kRowCandidates);
+        if (path_ok && rows_ok && (pick_path || path == current_path(c))) return finish(path, rows);
+    }
 
     int maxH = 0;
     for (int g = 0; g < c->G; ++g) maxH = std::max<int>(maxH, (int)c->H[g]);

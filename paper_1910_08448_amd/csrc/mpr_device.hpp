@@ -80,13 +80,7 @@ enum { F_ENERGY = 1, F_ACC = 2, F_DEC = 4 };
 enum { DEC_OR = 1, DEC_ACCEPT = 2, DEC_OUTSIDE = 4 };
 
 constexpr int kWave = 64;
-#ifndef MPR_PREFETCH_ROWS
-#define MPR_PREFETCH_ROWS 1
-#endif
-constexpr int kPrefetchRows = MPR_PREFETCH_ROWS;   // rows of both colours loaded ahead of use
-#ifndef MPR_SKEW
-#define MPR_SKEW 1
-#endif
+constexpr int kPrefetchRows = 1;   // rows of both colours loaded ahead of use (2-4 measured no faster)
 constexpr int kOutPairs = 60;      // output pairs per wave (2 halo lanes on each side)
 constexpr int kWavesPerBlock = 4;
 
@@ -782,7 +776,6 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
         }
     };
 
-#if MPR_SKEW
     // Skewed pipeline: iteration k updates colour 0 at row k and colour 1 at row k - 2.  The two
     // updates share no data (colour 1 at row k - 2 needs the new colour 0 of rows k - 3 ... k - 1
     // only), so in the steady state they form one branch-free block the scheduler interleaves:
@@ -860,67 +853,6 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
     for (; k <= ya + 1 && k <= yb; ++k) step(k, true, true, false);
     for (; k <= yb - 1; ++k) step(k, false, true, true);
     for (; k <= yb + 1; ++k) step(k, true, k <= yb, k - 2 >= ya);
-#else
-    // window: colour-1 old rows k-1, k, k+1; colour-0 new rows k-2, k-1, k
-    Pair v0_cur, v0_next, v1_m1, v1_0, v1_p1;
-    RowCS<F> w1_m1, w1_0, w1_p1;
-    RowCS<F> w0_m2, w0_m1, w0_0;
-    Pair n0_m1, n0_0;
-    int d0_m1a = 0, d0_m1b = 0, d0_0a = 0, d0_0b = 0;
-
-    v1_0 = load_pair(1, ya - 2);
-    w1_0 = cs_of(v1_0, ya - 2, 1);
-    v1_p1 = load_pair(1, ya - 1);
-    w1_p1 = cs_of(v1_p1, ya - 1, 1);
-    v0_next = load_pair(0, ya - 1);
-    w0_m1 = zero;
-    w0_0 = zero;
-    n0_0 = Pair{0, 0};
-    Pair pf1[kPrefetchRows], pf0[kPrefetchRows];
-#pragma unroll
-    for (int d = 0; d < kPrefetchRows; ++d) {
-        pf1[d] = load_ahead(1, ya + d);
-        pf0[d] = load_ahead(0, ya + d);
-    }
-
-    // iteration k: load row k+1, colour-0 update of row k, colour-1 update and store of row k-1
-    for (int k = ya - 1; k <= yb; ++k) {
-        w1_m1 = w1_0; w1_0 = w1_p1;
-        v1_m1 = v1_0; v1_0 = v1_p1;
-        w0_m2 = w0_m1; w0_m1 = w0_0;
-        n0_m1 = n0_0;
-        d0_m1a = d0_0a; d0_m1b = d0_0b;
-        v0_cur = v0_next;
-        v1_p1 = pf1[0];
-        v0_next = pf0[0];
-#pragma unroll
-        for (int d = 0; d + 1 < kPrefetchRows; ++d) {
-            pf1[d] = pf1[d + 1];
-            pf0[d] = pf0[d + 1];
-        }
-        pf1[kPrefetchRows - 1] = load_ahead(1, k + 1 + kPrefetchRows);
-        pf0[kPrefetchRows - 1] = load_ahead(0, k + 1 + kPrefetchRows);
-        w1_p1 = cs_of(v1_p1, k + 1, 1);
-        if (row_ok(k)) {
-            F e_unused;
-            update_row(v0_cur, w1_m1, w1_0, w1_p1, k, 0, n0_0, w0_0, d0_0a, d0_0b, e_unused);
-        } else {
-            n0_0 = v0_cur;
-            w0_0 = zero;
-            d0_0a = d0_0b = 0;
-        }
-        const int y = k - 1;
-        if (y >= ya) {
-            Pair n1;
-            RowCS<F> cs1;
-            int d1a, d1b;
-            F e;
-            update_row(v1_m1, w0_m2, w0_m1, w0_0, y, 1, n1, cs1, d1a, d1b, e);
-            finish_row(y, n0_m1, d0_m1a, d0_m1b, n1, d1a, d1b, e);
-        }
-    }
-
-#endif
 
     // wave reductions (inference sweeps only): exact integer sums, or a fixed-order float tree
     if (!(FLAGS & F_ENERGY)) return;

@@ -95,6 +95,20 @@ def _ptr(t):
     return t.ctypes.data_as(ctypes.c_void_p)
 
 
+def _check_dev(t, dtype, numel, what):
+    """A device buffer handed to the library: a contiguous CUDA tensor of the given dtype and
+    element count (the kernels read or write exactly that many elements, so anything else --
+    a host array, another dtype, a short tensor -- is refused here instead of reaching them)."""
+    if not hasattr(t, "data_ptr") or not getattr(t, "is_cuda", False):
+        raise TypeError("%s must be a CUDA tensor" % what)
+    if t.dtype != dtype:
+        raise TypeError("%s must have dtype %s, not %s" % (what, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s must hold %d elements, not %d" % (what, numel, t.numel()))
+
+
 def default_config(**kw):
     cfg = mpr_config()
     _lib.mpr_config_default(ctypes.byref(cfg))
@@ -176,15 +190,16 @@ class Context:
 
     def load(self, z, mask):
         """z: float64 CUDA tensor [H, W]; mask: uint8 CUDA tensor [H, W]."""
-        assert z.is_cuda and z.dtype == self.torch.float64 and z.is_contiguous()
-        assert mask.is_cuda and mask.dtype == self.torch.uint8 and mask.is_contiguous()
+        if z.dim() != 2 or tuple(mask.shape) != tuple(z.shape):
+            raise ValueError("z and mask must be [H, W] tensors of the same shape")
+        _check_dev(z, self.torch.float64, None, "z")
+        _check_dev(mask, self.torch.uint8, None, "mask")
         self._call("mpr_load", _lib.mpr_load, z.shape[0], z.shape[1], _ptr(z), _ptr(mask))
         self.shapes = [(int(z.shape[0]), int(z.shape[1]))]
 
     def batch_load(self, z_packed, mask_packed):
-        assert z_packed.is_cuda and z_packed.dtype == self.torch.float64
-        assert mask_packed.is_cuda and mask_packed.dtype == self.torch.uint8
-        assert z_packed.numel() == self.n_sites() == mask_packed.numel()
+        _check_dev(z_packed, self.torch.float64, self.n_sites(), "z_packed")
+        _check_dev(mask_packed, self.torch.uint8, self.n_sites(), "mask_packed")
         self._call("mpr_batch_load", _lib.mpr_batch_load, _ptr(z_packed), _ptr(mask_packed))
 
     def infer_temperature(self, n_equil, want_T=True):
@@ -226,6 +241,7 @@ class Context:
         t = self.torch
         if out is None:
             out = t.empty(self.n_sites(), dtype=t.float64, device="cuda")
+        _check_dev(out, t.float64, self.n_sites(), "out")
         self._call("mpr_get_predictions", _lib.mpr_get_predictions, _ptr(out))
         return out
 
@@ -251,8 +267,16 @@ class Context:
         return {"u": u, "acc": acc, "ctl": ctl, "meta": meta}
 
     def set_state(self, u=None, acc=None, ctl=None, meta=None):
+        n = self.n_sites() * self.n_chains
+        for name, a in (("u", u), ("acc", acc)):
+            if a is not None:
+                _check_dev(a, self.torch.float64, n, name)
         ctl = None if ctl is None else np.ascontiguousarray(ctl, dtype=np.float64)
         meta = None if meta is None else np.ascontiguousarray(meta, dtype=np.int64)
+        if ctl is not None and ctl.size != 2 * self.n_grids * self.n_chains:
+            raise ValueError("ctl must hold (T, alpha) for each of the %d chains" % (self.n_grids * self.n_chains))
+        if meta is not None and meta.size != 3:
+            raise ValueError("meta must hold 3 values")
         self._call("mpr_set_state", _lib.mpr_set_state, _ptr(u), _ptr(acc), _ptr(ctl), _ptr(meta))
 
     def debug_sweep(self, sweep):

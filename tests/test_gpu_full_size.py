@@ -3,13 +3,10 @@ sweep path, graph-captured sweep loops): the 1024 x 1024 workload with 33 % and 
 1000 inference + 100 averaging sweeps, one chain.
 
 * Decisions of whole sweeps from identical states against the FP64 oracle (every site).
-* Whole predictions against the oracle's stored run (tests/golden/oracle_reference.json, written
-  by tests/golden/make_oracle_reference.py, which calls only the oracle): FP64 to rounding of the
-  energy sums, FP32 and FP16 within 1 % of the oracle's MAE against the truth.
+(Whole predictions against the oracle's stored runs of every benchmark workload are in
+test_gpu_oracle_runs.py.)
 """
-import json
 import math
-import os
 
 import numpy as np
 import pytest
@@ -21,7 +18,6 @@ from oracle import oracle as O                      # noqa: E402
 from paper_1910_08448_amd import synth              # noqa: E402
 
 TWO_PI = 2.0 * math.pi
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_reference.json")
 
 
 @pytest.fixture(scope="module")
@@ -74,21 +70,3 @@ def test_full_size_decisions_match_oracle(mpr, workloads, precision):
         same = (dg == do) & free
         assert np.quantile(np.abs(ug - uo)[same], 0.99 if precision else 1.0) <= tol
         ctx.set_state(u=_dev(uo.reshape(-1), torch.float64))   # continue from the oracle's state
-
-
-@pytest.mark.parametrize("p", [0.33, 0.66])
-@pytest.mark.parametrize("precision,mae_tol", [(0, 1e-6), (1, 1e-2), (2, 1e-2)])
-def test_full_size_predictions_match_stored_oracle_run(mpr, workloads, p, precision, mae_tol):
-    ref = json.load(open(GOLDEN))["grid1024_p%.2f" % p]
-    w = workloads[p]
-    ctx = _ctx(mpr, w, seed=ref["mc_seed"], precision=precision)
-    T = ctx.infer_temperature(ref["n_equil"])
-    ctx.run(ref["n_avg"])
-    zhat = ctx.predictions().cpu().numpy().reshape(w["z"].shape)
-    m = w["mask"] == 0
-    err = zhat[m] - w["truth"][m]
-    mae = float(np.abs(err).mean())
-    assert abs(mae / ref["mae"] - 1.0) <= mae_tol, (mae, ref["mae"])
-    assert np.array_equal(zhat[~m], w["z"][~m])
-    if precision == 0:
-        assert abs(T[0] / ref["T_hat"] - 1.0) <= 1e-8

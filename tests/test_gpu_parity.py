@@ -46,10 +46,10 @@ def _gpu_ctx(mpr, z, mask, **cfg):
 
 
 def _decisions_case(mpr, H, W, boundary, n_chains, precision, seed, T=0.08, alpha=0.4, sweeps=3,
-                    mode=1):
-    truth, z, mask = _field(H, W, seed)
+                    mode=1, p=0.33, **gpu_cfg):
+    truth, z, mask = _field(H, W, seed, p=p)
     kw = dict(boundary=boundary, n_chains=n_chains, seed=seed + 5, alpha0=alpha)
-    ctx = _gpu_ctx(mpr, z, mask, precision=precision, sweep_mode=mode, **kw)
+    ctx = _gpu_ctx(mpr, z, mask, precision=precision, sweep_mode=mode, **kw, **gpu_cfg)
     orc = O.Oracle(n_threads=2, **kw)
     orc.load(z, mask)
     u0 = synth.random_state(n_chains, mask, seed + 7)
@@ -597,20 +597,27 @@ def test_sparse_colour_without_prediction_sites(mpr):
     assert np.abs(zs - zf)[m].mean() <= 1e-6 * rng_z
 
 
-@pytest.mark.parametrize("precision", [0, 1, 2, 3])
-def test_tiled_equals_sparse_bitwise(mpr, precision):
+@pytest.mark.parametrize("precision,func_prec,p", [(0, -1, 0.33), (1, -1, 0.33), (2, -1, 0.33),
+                                                   (3, -1, 0.33), (1, 0, 0.33), (1, 0, 0.9)])
+def test_tiled_equals_sparse_bitwise(mpr, precision, func_prec, p):
     """The tiled path sums the energy by the same bond kinds and per-site terms as the compacted
     path, so whole runs (temperature trajectories, estimates, predictions) agree bit for bit;
-    a batch of uneven grids with two chains each, open and periodic."""
+    a batch of uneven grids with two chains each, open and periodic; every storage precision
+    with its default functions, and FP32 storage with double-precision functions (the paper's
+    SDD setting, whose tiled kernel stages 16-row tiles) at 33 % and at the paper's 90 %
+    missing."""
     for boundary, shapes in ((0, [(45, 70), (17, 300), (2, 3), (64, 64)]),
                              (1, [(16, 24), (34, 264), (2, 4)])):
-        fields = [_field(h, w, 500 + i) for i, (h, w) in enumerate(shapes)]
+        if p > 0.5:     # grids too small to keep two distinct sample values at 90 % missing
+            shapes = [(h, w) for h, w in shapes if h * w >= 256]
+        fields = [_field(h, w, 500 + i, p=p) for i, (h, w) in enumerate(shapes)]
         z = np.concatenate([f[1].ravel() for f in fields])
         m = np.concatenate([f[2].ravel() for f in fields])
         res = []
         for mode in (mpr.SWEEP_SPARSE, mpr.SWEEP_TILED):
             ctx = mpr.Context(shapes=shapes, stream=torch.cuda.Stream(), seed=4, n_chains=2,
-                              precision=precision, boundary=boundary, sweep_mode=mode)
+                              precision=precision, func_prec=func_prec, boundary=boundary,
+                              sweep_mode=mode)
             ctx.batch_load(_dev(z, torch.float64), _dev(m, torch.uint8))
             assert ctx.sweep_mode() == mode
             T = ctx.infer_temperature(24)
@@ -716,3 +723,64 @@ def test_contexts_on_two_host_threads(mpr):
         run(i, alone)
     for i in range(2):
         assert both[i] is not None and np.array_equal(both[i], alone[i])
+
+
+@pytest.mark.parametrize("mode", [1, 2, 3])
+@pytest.mark.parametrize("p", [0.33, 0.9])
+def test_fp32_storage_double_functions_match_oracle(mpr, mode, p):
+    """FP32 storage with double-precision functions (the paper's SDD setting) on every sweep
+    path, at 33 % and at the paper's 90 % missing: from identical states (rounded to FP32 on
+    the device) the decisions equal the oracle's on >= 99.9 % of the prediction sites and the
+    equal ones agree to a few FP32 roundings of the stored angles (1e-6 turns, 99.9 %)."""
+    mask, rounds = _decisions_case(mpr, 70, 130, 0, 2, mpr.FP32, seed=77, mode=mode, p=p,
+                                   func_prec=mpr.PREC_DOUBLE)
+    free = np.broadcast_to(mask == 0, rounds[0][0].shape)
+    for dg, do, ug, uo in rounds:
+        assert not dg[~free].any()
+        assert (dg == do)[free].mean() >= 0.999
+        agree = free & (dg == do)
+        assert np.quantile(np.abs(ug - uo)[agree], 0.999) <= 1e-6
+
+
+def test_automatic_path_choice_double_functions_at_90_percent(mpr):
+    """AUTO takes the tiled path for a small grid with FP32 storage, double-precision functions
+    and 90 % prediction sites, and its run equals the compacted path's bit for bit."""
+    truth, z, mask = _field(96, 136, 8, p=0.9)
+    res = []
+    for mode in (mpr.SWEEP_AUTO, mpr.SWEEP_SPARSE):
+        ctx = _gpu_ctx(mpr, z, mask, precision=mpr.FP32, func_prec=mpr.PREC_DOUBLE, seed=3,
+                       n_chains=2, sweep_mode=mode)
+        if mode == mpr.SWEEP_AUTO:
+            assert ctx.sweep_mode() == mpr.SWEEP_TILED
+        T = ctx.infer_temperature(20)
+        ctx.run(6)
+        res.append((T, ctx.trace(0), ctx.predictions().cpu().numpy()))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+    assert np.array_equal(res[0][2], res[1][2])
+
+
+def test_binding_refuses_buffers_the_kernels_cannot_use(mpr):
+    """The binding checks every device buffer it hands to the library (type, dtype, contiguity,
+    element count) before the call, so a host array or a short tensor never reaches a kernel."""
+    truth, z, mask = _field(12, 16, 4)
+    ctx = _gpu_ctx(mpr, z, mask, precision=mpr.FP32)
+    n = 12 * 16
+    with pytest.raises(TypeError):
+        ctx.set_state(u=np.zeros(n))
+    with pytest.raises(TypeError):
+        ctx.set_state(u=torch.zeros(n, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        ctx.set_state(u=torch.zeros(n - 1, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        ctx.set_state(acc=torch.zeros(2 * n, dtype=torch.float64, device="cuda")[::2])
+    ctx.set_temperature(0.1)
+    ctx.run(2)
+    with pytest.raises(ValueError):
+        ctx.predictions(out=torch.empty(n - 1, dtype=torch.float64, device="cuda"))
+    with pytest.raises(TypeError):
+        ctx.predictions(out=torch.empty(n, dtype=torch.float64))
+    with pytest.raises(TypeError):
+        ctx.load(_dev(z, torch.float32), _dev(mask, torch.uint8))
+    out = ctx.predictions(out=torch.empty(n, dtype=torch.float64, device="cuda"))
+    assert np.isfinite(out.cpu().numpy()).all()
