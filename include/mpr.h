@@ -190,6 +190,19 @@ int mpr_energy_curve(const mpr_config* cfg, void* hip_stream, int32_t side, int3
 int mpr_set_temperature_curve(mpr_ctx* ctx, int32_t n_T, const double* T_host,
                               const double* e_host, double* T_out);
 
+/* For callers that cannot allocate device memory (code that runs where hipMalloc is not
+ * allowed, tight serving loops): mpr_set_temperature_curve with the same arguments, results and
+ * error codes, which allocates nothing.  The curve table and the temperatures read back stage
+ * through a static device array of 8192 doubles (64 KiB) that each device holds until the
+ * process ends: 2 n_T + (T_out ? n_grids * n_chains : 0) must not exceed 8192 (EINVAL
+ * otherwise, context unchanged).  Every call writes all of the array it reads, so nothing of an
+ * earlier call leaks into the next; the array is shared by every context on the device, so
+ * calls that overlap on one device (two host threads, two streams) race and must be
+ * serialised by the caller.  The context's device must be the current device (EINVAL
+ * otherwise).  Synchronises the context's stream. */
+int mpr_set_temperature_curve_noalloc(mpr_ctx* ctx, int32_t n_T, const double* T_host,
+                                      const double* e_host, double* T_out);
+
 /* n sweeps at the current temperatures and windows, without averaging (no control). */
 int mpr_burn_in(mpr_ctx* ctx, int32_t n);
 

@@ -293,6 +293,14 @@ __global__ void k_curve_temperature(GcCtl* ctl, int n_gc, const double* T, const
     ctl[i].T = r;
 }
 
+// each (grid, chain)'s temperature into a plain array (the allocation-free curve entry point
+// reads it back from its static scratch)
+__global__ void k_gather_T(const GcCtl* ctl, int n_gc, double* out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_gc) out[i] = ctl[i].T;
+}
+
 __global__ void k_advance(RunCtl* run, int64_t n) { run->base_sweep += n; }
 __global__ void k_set_base(RunCtl* run, int64_t v) { run->base_sweep = v; }
 
@@ -657,6 +665,32 @@ template <class S, class F> TiledFn pick_tiled(int flags, bool per, bool large)
 }
 
 }  // namespace
+
+// ------------------------------------------------------------------ static scratch
+// Device memory of mpr_set_temperature_curve_noalloc: the curve table (T, e) and the gathered
+// temperatures, in a file-scope array each device holds for the life of the process.  Host code
+// never uses the symbol's name as an address: each device's copy lives at its own address,
+// looked up once per device (hipGetSymbolAddress with that device current) and kept here.
+constexpr int kScratchDoubles = 8192;                 // 64 KiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+// this device's copy of `scratch` (looked up at the first call on the device)
+static hipError_t scratch_address(int device, double** out)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = (double*)p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 // ------------------------------------------------------------------ context
 enum { PH_EMPTY = 0, PH_LOADED = 1, PH_TEMPERED = 2, PH_AVERAGED = 3 };
@@ -1718,6 +1752,44 @@ int mpr_set_temperature_curve(mpr_ctx* c, int32_t n_T, const double* T_host, con
         HIPCHK(c, hipStreamSynchronize(c->stream));
         for (size_t i = 0; i < ctl.size(); ++i) T_out[i] = ctl[i].T;
     }
+    return MPR_OK;
+}
+
+int mpr_set_temperature_curve_noalloc(mpr_ctx* c, int32_t n_T, const double* T_host,
+                                      const double* e_host, double* T_out)
+{
+    int rc = usable(c);
+    if (rc) return rc;
+    if (c->phase < PH_LOADED) return fail(c, MPR_ESTATE, "no data loaded");
+    if (n_T < 1 || !T_host || !e_host) return fail(c, MPR_EINVAL, "bad curve arguments");
+    const int n_gc = (int)c->gcs.size();
+    if (2 * (int64_t)n_T + (T_out ? n_gc : 0) > kScratchDoubles)
+        return fail(c, MPR_EINVAL, "curve of %d points%s exceeds the static scratch of %d doubles",
+                    n_T, T_out ? " and the chains' temperatures" : "", kScratchDoubles);
+    for (int i = 0; i < n_T; ++i)
+        if (!(T_host[i] > 0.0) || !std::isfinite(T_host[i]) || !std::isfinite(e_host[i]) ||
+            (i > 0 && !(T_host[i] > T_host[i - 1])))
+            return fail(c, MPR_EINVAL, "curve temperatures must be finite, positive and increasing");
+    int dev = -1;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev != c->device) return fail(c, MPR_EINVAL, "the context's device is not the current device");
+    double* tab = nullptr;
+    HIPCHK(c, scratch_address(dev, &tab));
+    // every value the kernels read is written here first: nothing of an earlier call is used
+    HIPCHK(c, hipMemcpyAsync(tab, T_host, n_T * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(tab + n_T, e_host, n_T * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_curve_temperature, dim3((n_gc + 255) / 256), dim3(256), 0, c->stream,
+                       c->d_ctl, n_gc, tab, tab + n_T, n_T);
+    if (T_out)
+        hipLaunchKernelGGL(k_gather_T, dim3((n_gc + 255) / 256), dim3(256), 0, c->stream, c->d_ctl,
+                           n_gc, tab + 2 * n_T);
+    HIPCHK(c, hipGetLastError());
+    if (T_out)
+        HIPCHK(c, hipMemcpyAsync(T_out, tab + 2 * n_T, n_gc * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+    // the host arrays may be released, and another call may reuse the scratch, after this
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->phase = std::max(c->phase, (int)PH_TEMPERED);
     return MPR_OK;
 }
 

@@ -57,6 +57,7 @@ _SIG = {
     "mpr_equilibrate": (ctypes.c_int, [_vp, _i32, _vp]),
     "mpr_energy_curve": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _i32, _i32, _vp, _vp]),
     "mpr_set_temperature_curve": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp]),
+    "mpr_set_temperature_curve_noalloc": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp]),
     "mpr_burn_in": (ctypes.c_int, [_vp, _i32]),
     "mpr_run": (ctypes.c_int, [_vp, _i32]),
     "mpr_get_predictions": (ctypes.c_int, [_vp, _vp]),

@@ -98,5 +98,5 @@ def test_energy_curve_and_sweep_mode_host_validation(M):
     assert M.mpr_energy_curve(ref, None, 8, 2, T, 2 ** 31 - 1, 1, e, None) == M.EINVAL
     for b in bad_T:
         assert M.mpr_energy_curve(ref, None, 8, 1, b, 1, 1, e, None) == M.EINVAL
-    for fn in (M.mpr_equilibrate, M.mpr_set_temperature_curve):
+    for fn in (M.mpr_equilibrate, M.mpr_set_temperature_curve, M.mpr_set_temperature_curve_noalloc):
         assert fn(None, *([1] + [None] * (fn.argtypes.__len__() - 2))) == M.EINVAL
