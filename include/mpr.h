@@ -91,8 +91,18 @@ typedef struct mpr_config {
     int32_t graph_sweeps;     /* sweeps per captured HIP graph, 0 = automatic,
                                  -1 = launch kernels without graphs                   */
     int32_t sweep_mode;       /* mpr_sweep_mode: how a sweep visits the sites          */
-    int32_t reserved[5];
+    int32_t tile_shape;       /* tiled path's block shape: 0 = automatic (rule, or the
+                                 autotuner with tile_rows = -1), 1 + mpr_tile_shape
+                                 forces one (all but MPR_TILE_W4_BASE need
+                                 single-precision functions, EINVAL otherwise)        */
+    int32_t reserved[4];
 } mpr_config;
+
+/* Block shapes of the tiled path: waves per block and tile height (the base height is 16 rows,
+ * 8 for 8-byte spins with single-precision functions; tall tiles have twice as many rows). */
+typedef enum mpr_tile_shape {
+    MPR_TILE_W4_BASE = 0, MPR_TILE_W8_TALL = 1, MPR_TILE_W4_TALL = 2, MPR_TILE_W8_BASE = 3
+} mpr_tile_shape;
 
 /* How a sweep visits the sites.
  * FUSED: one launch per sweep over every site in row blocks, both colours in one pass with halo
@@ -101,11 +111,12 @@ typedef struct mpr_config {
  *   at load; needs double-precision energy and grids with H < 65536 and
  *   ceil(ceil(W / 2) / 2) * 2 < 65536.
  * TILED: one launch per sweep, one block per tile of 128 columns staged in LDS with its halo
- *   (eight-wave blocks on tiles of 32 rows, 16 with 8-byte spins, while the grids hold fewer
- *   than 2048 tiles of half that height; otherwise four-wave blocks on tiles of 16 rows, 8 with
- *   8-byte spins, and with double-precision functions four-wave blocks on 16-row tiles); each colour's prediction sites are compacted into
- *   a list inside the block, and the colour-0 sites around the tile are recomputed; needs
- *   double-precision energy.
+ *   (the block shape, mpr_tile_shape, unless forced or tuned: eight-wave blocks on tiles of 32
+ *   rows, 16 with 8-byte spins, while the grids hold fewer than 2048 tiles of half that height;
+ *   otherwise four-wave blocks on tiles of 16 rows, 8 with 8-byte spins; with double-precision
+ *   functions always four-wave blocks on 16-row tiles); each colour's prediction sites are
+ *   compacted into a list inside the block, and the colour-0 sites around the tile are
+ *   recomputed; needs double-precision energy.
  * All three take identical decisions from identical states; SPARSE and TILED also sum the
  * energy identically (bitwise equal results), while FUSED groups the bonds differently, so its
  * temperature trajectories agree with theirs to rounding, not bitwise.
@@ -259,15 +270,27 @@ int mpr_bench_sweeps(mpr_ctx* ctx, int32_t n);
 
 /* Autotuner: times n_sweeps inference-variant sweeps of each candidate from the current state,
  * which is restored after each, and keeps the fastest.  Candidates: the fused path's rows per
- * work item (the six best of 2 ... 256 by a cost model; results do not depend on the choice),
- * and, when the configuration's sweep_mode is MPR_SWEEP_AUTO, the sweep path itself (fused,
- * compacted where possible, tiled where possible; mpr_get_sweep_mode reports the choice; the
- * path changes only the rounding of the energy sums, see mpr_sweep_mode).  Winners are
- * remembered per shape, precision, sweep_mode and percentage of prediction sites in the process,
- * and in the text file named by the environment variable MPR_TUNE_CACHE if it is set.
+ * work item (the six best of 2 ... 256 by a cost model), when the configuration's sweep_mode is
+ * MPR_SWEEP_AUTO the sweep path itself (fused, compacted where possible, tiled where possible;
+ * the path changes only the rounding of the energy sums, see mpr_sweep_mode), on the tiled path
+ * its block shape (the four mpr_tile_shape values with single-precision functions, unless
+ * tile_shape forces one), and, when graph_sweeps is 0, the sweeps per captured graph (16, 32,
+ * 64; timed as graph replays).  Results do not depend on the rows, the tile shape or the graph
+ * length.  mpr_get_tuning reports the choice.  Winners are remembered per shape, precision,
+ * sweep_mode, tile_shape, graph_sweeps and percentage of prediction sites in the process, and in
+ * the text file named by the environment variable MPR_TUNE_CACHE if it is set (an entry this
+ * context cannot use is ignored and tuned again).
  * mpr_config tile_rows = -1 runs it at every load (8 sweeps; a remembered winner costs no
  * timing).  *rows_out (may be NULL) receives the fused path's rows per work item. */
 int mpr_autotune(mpr_ctx* ctx, int32_t n_sweeps, int32_t* rows_out);
+
+/* The configuration the context sweeps with (chosen at the last load by the rule, the
+ * configuration or the autotuner): *path_out the sweep path (MPR_SWEEP_FUSED, _SPARSE or
+ * _TILED), *rows_out the fused path's rows per work item, *tile_shape_out the tiled path's
+ * mpr_tile_shape (-1 on the other paths), *graph_sweeps_out the sweeps per captured graph (-1:
+ * no graphs).  Any pointer may be NULL; ESTATE before a load. */
+int mpr_get_tuning(mpr_ctx* ctx, int32_t* path_out, int32_t* rows_out, int32_t* tile_shape_out,
+                   int32_t* graph_sweeps_out);
 
 /* The sweep path chosen at the last load (MPR_SWEEP_FUSED, _SPARSE or _TILED); ESTATE before
  * a load. */

@@ -17,6 +17,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 using namespace mpr;
@@ -647,21 +648,34 @@ template <class S, class F> SparseFn pick_sparse(int flags, bool per, int colour
 
 using TiledFn = void (*)(TiledArgs);
 
-template <class S, class F, bool PER, int NW> TiledFn pick_tiled_b(int flags)
+template <class S, class F, bool PER, int NW, bool TALL> TiledFn pick_tiled_b(int flags)
 {
     switch (flags) {
-    case 0: return k_tiled<S, F, 0, PER, NW>;
-    case F_ENERGY: return k_tiled<S, F, F_ENERGY, PER, NW>;
-    case F_ACC: return k_tiled<S, F, F_ACC, PER, NW>;
-    default: return k_tiled<S, F, F_DEC, PER, NW>;
+    case 0: return k_tiled<S, F, 0, PER, NW, TALL>;
+    case F_ENERGY: return k_tiled<S, F, F_ENERGY, PER, NW, TALL>;
+    case F_ACC: return k_tiled<S, F, F_ACC, PER, NW, TALL>;
+    default: return k_tiled<S, F, F_DEC, PER, NW, TALL>;
     }
 }
 
-template <class S, class F> TiledFn pick_tiled(int flags, bool per, bool large)
+template <class S, class F, bool PER> TiledFn pick_tiled_s(int flags, int shape)
 {
-    if (large)
-        return per ? pick_tiled_b<S, F, true, kTileWavesLarge>(flags) : pick_tiled_b<S, F, false, kTileWavesLarge>(flags);
-    return per ? pick_tiled_b<S, F, true, kTileWavesSmall>(flags) : pick_tiled_b<S, F, false, kTileWavesSmall>(flags);
+    // double-precision functions: four-wave blocks on base-height tiles only
+    if constexpr (sizeof(F) == 8) {
+        return pick_tiled_b<S, F, PER, 4, false>(flags);
+    } else {
+        switch (shape) {
+        case kShapeW8Tall: return pick_tiled_b<S, F, PER, 8, true>(flags);
+        case kShapeW4Tall: return pick_tiled_b<S, F, PER, 4, true>(flags);
+        case kShapeW8Base: return pick_tiled_b<S, F, PER, 8, false>(flags);
+        default: return pick_tiled_b<S, F, PER, 4, false>(flags);
+        }
+    }
+}
+
+template <class S, class F> TiledFn pick_tiled(int flags, bool per, int shape)
+{
+    return per ? pick_tiled_s<S, F, true>(flags, shape) : pick_tiled_s<S, F, false>(flags, shape);
 }
 
 }  // namespace
@@ -733,7 +747,7 @@ struct mpr_ctx {
     int cur = 0;                 // state buffer holding the current configuration
     int64_t next_sweep = 0, n_avg = 0;
     int phase = PH_EMPTY;
-    std::map<std::pair<int, int>, hipGraphExec_t> graphs;   // (mode, cur) -> graph of K sweeps
+    std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;   // (mode, cur, length) -> graph
     int graph_k = 0;
     std::vector<int64_t> alloc_sig;                          // shapes the buffers were sized for
     int rows = 16;                                           // rows per work item
@@ -758,7 +772,9 @@ struct mpr_ctx {
     int4* d_tiles = nullptr;
     int64_t tiles_cap = 0;
     int32_t n_tiles = 0, tiles_ntx = 0;
-    bool tiles_big = false;     // eight-wave blocks on tiles of twice the base height
+    int tile_shape = kShapeW4Base;   // (waves per block, tile height) of the tiled path
+    int tile_shape_req = -1;         // shape asked for: forced by the configuration or picked by
+                                     // the autotuner; -1 = the automatic rule
 };
 
 static const char* kStatusText[] = {
@@ -805,6 +821,7 @@ static int check_config(const mpr_config* c)
     if (!(c->T_min > 0.0) || !(c->T_max >= c->T_min) || !std::isfinite(c->T_max)) return MPR_EINVAL;
     if (c->tile_rows < -1 || c->grid_offset < 0) return MPR_EINVAL;
     if (c->sweep_mode < MPR_SWEEP_AUTO || c->sweep_mode > MPR_SWEEP_TILED) return MPR_EINVAL;
+    if (c->tile_shape < 0 || c->tile_shape > kTileShapes) return MPR_EINVAL;
     if ((c->sweep_mode == MPR_SWEEP_SPARSE || c->sweep_mode == MPR_SWEEP_TILED) &&
         c->energy_prec == MPR_PREC_SINGLE)
         return MPR_EINVAL;
@@ -1078,16 +1095,19 @@ template <class S, class F> static void launch_econst(mpr_ctx* c)
 static int build_econst(mpr_ctx* c);
 
 // tiles of the tiled path: per (grid, chain), row blocks of the tile height x column blocks of
-// kTileCols plane columns, row-major (neighbouring tiles get neighbouring block numbers).  With
-// single-precision functions and fewer than kTileWavesSwitch tiles of the base height, the
-// eight-wave blocks and their tiles of twice that height; else four-wave blocks.
-template <class S, class F> static int build_tiles_t(mpr_ctx* c)
+// kTileCols plane columns, row-major (neighbouring tiles get neighbouring block numbers).  The
+// shape: forced by the configuration or chosen by the autotuner (shape >= 0), else the rule --
+// with single-precision functions and fewer than kTileWavesSwitch tiles of the base height,
+// eight-wave blocks on tiles of twice that height; else four-wave blocks on base-height tiles.
+template <class S, class F> static int build_tiles_t(mpr_ctx* c, int shape)
 {
     int64_t base = 0;
     for (const GcDesc& d : c->gcs)
         base += (int64_t)((d.H + tile_rows<S, F>() - 1) / tile_rows<S, F>()) * ((d.wc + kTileCols - 1) / kTileCols);
-    c->tiles_big = sizeof(F) == 4 && base < kTileWavesSwitch;
-    const int TY = c->tiles_big ? tile_rows_for<S, F, kTileWavesSmall>() : tile_rows_for<S, F, kTileWavesLarge>();
+    if (sizeof(F) == 8) shape = kShapeW4Base;
+    else if (shape < 0) shape = base < kTileWavesSwitch ? kShapeW8Tall : kShapeW4Base;
+    c->tile_shape = shape;
+    const int TY = shape_tall(shape) ? tile_rows_for<S, F, true>() : tile_rows_for<S, F, false>();
     std::vector<int4> t;
     for (int i = 0; i < (int)c->gcs.size(); ++i) {
         const GcDesc& d = c->gcs[i];
@@ -1107,13 +1127,13 @@ template <class S, class F> static int build_tiles_t(mpr_ctx* c)
     return build_econst(c);
 }
 
-static int build_tiles(mpr_ctx* c)
+static int build_tiles(mpr_ctx* c, int shape)
 {
     switch (c->sprec) {
-    case MPR_FP64: return c->fsingle ? build_tiles_t<double, float>(c) : build_tiles_t<double, double>(c);
-    case MPR_FP32: return c->fsingle ? build_tiles_t<float, float>(c) : build_tiles_t<float, double>(c);
-    case MPR_FIX16: return build_tiles_t<Fix15, float>(c);
-    default: return build_tiles_t<_Float16, float>(c);
+    case MPR_FP64: return c->fsingle ? build_tiles_t<double, float>(c, shape) : build_tiles_t<double, double>(c, shape);
+    case MPR_FP32: return c->fsingle ? build_tiles_t<float, float>(c, shape) : build_tiles_t<float, double>(c, shape);
+    case MPR_FIX16: return build_tiles_t<Fix15, float>(c, shape);
+    default: return build_tiles_t<_Float16, float>(c, shape);
     }
 }
 
@@ -1260,7 +1280,7 @@ static int apply_path(mpr_ctx* c, int path)
     }
     c->sparse = sparse;
     c->tiled = tiled;
-    return sparse ? build_lists(c) : (tiled ? build_tiles(c) : MPR_OK);
+    return sparse ? build_lists(c) : (tiled ? build_tiles(c, c->tile_shape_req) : MPR_OK);
 }
 
 // the sweep path for the loaded data (sweep_mode, or the automatic rule)
@@ -1322,6 +1342,10 @@ static int create_common(const mpr_config* cfg, void* stream, mpr_ctx** out)
     c->fsingle = cfg->func_prec == MPR_PREC_DEFAULT ? cfg->precision != MPR_FP64
                                                     : cfg->func_prec == MPR_PREC_SINGLE;
     c->esingle = cfg->energy_prec == MPR_PREC_SINGLE;
+    if (cfg->tile_shape > 0) {   // a forced tile shape; the eight-wave and tall ones need single-precision functions
+        if (!c->fsingle && cfg->tile_shape - 1 != kShapeW4Base) { delete c; return MPR_EINVAL; }
+        c->tile_shape_req = cfg->tile_shape - 1;
+    }
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return MPR_EHIP; }
     c->graph_k = cfg->graph_sweeps == 0 ? 32 : cfg->graph_sweeps;
     if (c->graph_k > 0 && (c->graph_k & 1)) c->graph_k += 1;
@@ -1472,19 +1496,17 @@ static SweepFn sweep_fn(const mpr_ctx* c, int flags)
 
 // the tiles built for the loaded data fix the block (four waves also with double-precision
 // functions, whose registers leave three waves per SIMD)
-static int tile_waves(const mpr_ctx* c)
-{
-    return c->tiles_big ? kTileWavesSmall : kTileWavesLarge;
-}
+static int tile_waves(const mpr_ctx* c) { return shape_waves(c->tile_shape); }
 
 static TiledFn tiled_fn(const mpr_ctx* c, int flags)
 {
-    const bool per = c->cfg.boundary == MPR_PERIODIC, large = tile_waves(c) == kTileWavesLarge;
+    const bool per = c->cfg.boundary == MPR_PERIODIC;
+    const int sh = c->tile_shape;
     switch (c->sprec) {
-    case MPR_FP64: return c->fsingle ? pick_tiled<double, float>(flags, per, large) : pick_tiled<double, double>(flags, per, large);
-    case MPR_FP32: return c->fsingle ? pick_tiled<float, float>(flags, per, large) : pick_tiled<float, double>(flags, per, large);
-    case MPR_FIX16: return pick_tiled<Fix15, float>(flags, per, large);
-    default: return pick_tiled<_Float16, float>(flags, per, large);
+    case MPR_FP64: return c->fsingle ? pick_tiled<double, float>(flags, per, sh) : pick_tiled<double, double>(flags, per, sh);
+    case MPR_FP32: return c->fsingle ? pick_tiled<float, float>(flags, per, sh) : pick_tiled<float, double>(flags, per, sh);
+    case MPR_FIX16: return pick_tiled<Fix15, float>(flags, per, sh);
+    default: return pick_tiled<_Float16, float>(flags, per, sh);
     }
 }
 
@@ -1638,25 +1660,44 @@ static void enqueue_block(mpr_ctx* c, int mode, int n)
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, c->stream, c->d_run, (int64_t)n);
 }
 
+// launches the captured graph of `len` sweeps of `mode` from the current buffer (captured at its
+// first use and kept until the launch arguments it holds change)
+static int launch_graph(mpr_ctx* c, int mode, int len)
+{
+    const auto key = std::make_tuple(mode, c->cur, len);
+    hipGraphExec_t exec = nullptr;
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        enqueue_block(c, mode, len);
+        hipGraph_t graph = nullptr;
+        HIPCHK(c, hipStreamEndCapture(c->stream, &graph));
+        const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(c, e);
+        c->graphs[key] = exec;
+    } else exec = it->second;
+    HIPCHK(c, hipGraphLaunch(exec, c->stream));
+    return MPR_OK;
+}
+
 static int run_sweeps(mpr_ctx* c, int mode, int n)
 {
     int done = 0;
     const int K = c->graph_k;
-    if (K > 0 && n >= K) {
-        auto key = std::make_pair(mode, c->cur);
-        hipGraphExec_t exec = nullptr;
-        auto it = c->graphs.find(key);
-        if (it == c->graphs.end()) {
-            HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            enqueue_block(c, mode, K);
-            hipGraph_t graph = nullptr;
-            HIPCHK(c, hipStreamEndCapture(c->stream, &graph));
-            HIPCHK(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-            (void)hipGraphDestroy(graph);
-            c->graphs[key] = exec;
-        } else exec = it->second;
-        for (; done + K <= n; done += K) HIPCHK(c, hipGraphLaunch(exec, c->stream));
-        // K is even: the buffer parity is unchanged
+    if (K > 0) {
+        // whole graphs of K sweeps (K is even: the buffer parity is unchanged), then one graph of
+        // the remaining sweeps
+        for (; done + K <= n; done += K) {
+            const int rc = launch_graph(c, mode, K);
+            if (rc) return rc;
+        }
+        if (n - done >= 2) {
+            const int rc = launch_graph(c, mode, n - done);
+            if (rc) return rc;
+            if ((n - done) & 1) c->cur ^= flips(c);
+            done = n;
+        }
     }
     if (done < n) {
         enqueue_block(c, mode, n - done);
@@ -2079,17 +2120,22 @@ static std::mutex& tune_mutex()
     static std::mutex m;
     return m;
 }
-static std::map<std::string, int>& tune_cache()
+// A tuned choice: sweep path, rows per work item of the fused path, block shape of the tiled path
+// (-1: the automatic rule) and sweeps per captured graph (0: the configured value).
+struct TuneChoice { int path, rows, shape, graph_k; };
+
+static std::map<std::string, TuneChoice>& tune_cache()
 {
-    static std::map<std::string, int> m;
+    static std::map<std::string, TuneChoice> m;
     static bool loaded = false;
     if (!loaded) {
         loaded = true;
         if (const char* path = std::getenv("MPR_TUNE_CACHE")) {
             if (FILE* f = std::fopen(path, "r")) {
                 char key[256];
-                int rows;
-                while (std::fscanf(f, "%255s %d", key, &rows) == 2) m[key] = rows;
+                TuneChoice t;
+                while (std::fscanf(f, "%255s %d %d %d %d", key, &t.path, &t.rows, &t.shape, &t.graph_k) == 5)
+                    m[key] = t;
                 std::fclose(f);
             }
         }
@@ -2109,9 +2155,9 @@ static std::string tune_key(const mpr_ctx* c)
     // the path depends on the share of prediction sites: keyed to the percent
     const int pct = N > 0 ? (int)std::lround(100.0 * (double)P / (double)N) : 0;
     char buf[192];
-    std::snprintf(buf, sizeof buf, "s%d_f%d_e%d_b%d_c%d_g%d_m%d_p%d_%016llx", c->sprec, (int)c->fsingle,
-                  (int)c->esingle, c->cfg.boundary, c->C, c->G, c->cfg.sweep_mode, pct,
-                  (unsigned long long)h);
+    std::snprintf(buf, sizeof buf, "s%d_f%d_e%d_b%d_c%d_g%d_m%d_t%d_k%d_p%d_%016llx", c->sprec, (int)c->fsingle,
+                  (int)c->esingle, c->cfg.boundary, c->C, c->G, c->cfg.sweep_mode, c->cfg.tile_shape,
+                  c->cfg.graph_sweeps, pct, (unsigned long long)h);
     return buf;
 }
 
@@ -2128,42 +2174,65 @@ static int use_rows(mpr_ctx* c, int rows)
     return MPR_OK;
 }
 
+static const int kGraphCandidates[] = {16, 32, 64};
+static bool tune_graphs(const mpr_ctx* c) { return c->cfg.graph_sweeps == 0 && c->stream != nullptr; }
+
+// whether a remembered choice can be used by this context
+static bool choice_valid(const mpr_ctx* c, const TuneChoice& t, bool pick_path)
+{
+    const bool path_ok = t.path == MPR_SWEEP_FUSED || (t.path == MPR_SWEEP_SPARSE && sparse_possible(c)) ||
+                         (t.path == MPR_SWEEP_TILED && tiled_possible(c));
+    const bool rows_ok = std::find(std::begin(kRowCandidates), std::end(kRowCandidates), t.rows) !=
+                         std::end(kRowCandidates);
+    const bool shape_ok = t.shape == -1 || (t.shape >= 0 && t.shape < kTileShapes && (c->fsingle || t.shape == kShapeW4Base));
+    const bool graph_ok = t.graph_k == 0 || std::find(std::begin(kGraphCandidates), std::end(kGraphCandidates),
+                                                       t.graph_k) != std::end(kGraphCandidates);
+    return path_ok && rows_ok && shape_ok && graph_ok && (pick_path || t.path == current_path(c));
+}
+
 // Times n inference-variant sweeps of each candidate from the current state (restored after
-// each) and keeps the fastest: the row count of the fused path's work items, and with
-// sweep_mode AUTO the sweep path itself (fused, compacted, tiled).  Results do not depend on
-// the row count (tested bitwise); the path changes only the rounding of the energy sums.
-// Winners are cached per shape, precision and share of prediction sites as path * 1000 + rows.
+// each) and keeps the fastest: the row count of the fused path's work items; with sweep_mode AUTO
+// the sweep path itself (fused, compacted, tiled); on the tiled path, unless the configuration
+// forces one, its block shape (waves per block and tile height); and, when graph_sweeps is 0,
+// the sweeps per captured graph (timed as graph replays).  Results do not depend on the row
+// count, the tile shape or the graph length (tested bitwise); the path changes only the
+// rounding of the energy sums.  Winners are cached per shape, configuration and share of
+// prediction sites.
 static int autotune(mpr_ctx* c, int n, int* best_out)
 {
     const bool pick_path = c->cfg.sweep_mode == MPR_SWEEP_AUTO;
-    if (!pick_path && (c->sparse || c->tiled)) {   // no work-item shape on these paths
-        if (best_out) *best_out = c->rows;
-        return MPR_OK;
-    }
+    const bool pick_shape = c->cfg.tile_shape == 0;
     const std::string key = tune_key(c);
-    auto finish = [&](int path, int rows) -> int {
+    auto finish = [&](const TuneChoice& t) -> int {
         int rc = MPR_OK;
-        if (path == MPR_SWEEP_FUSED && rows != c->rows) rc = use_rows(c, rows);
-        if (!rc) rc = apply_path(c, path);
+        if (t.rows != c->rows) rc = use_rows(c, t.rows);
+        if (!rc && pick_shape) c->tile_shape_req = t.path == MPR_SWEEP_TILED ? t.shape : -1;
+        if (!rc) {
+            // a new tile shape changes the launches the graphs hold
+            for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+            c->graphs.clear();
+            rc = apply_path(c, t.path);
+        }
+        if (!rc && t.graph_k > 0 && tune_graphs(c)) c->graph_k = t.graph_k;
         if (best_out) *best_out = c->rows;
         return rc;
     };
-    int cached = -1;
     {
-        std::lock_guard<std::mutex> lock(tune_mutex());
-        auto& cache = tune_cache();
-        auto hit = cache.find(key);
-        if (hit != cache.end()) cached = hit->second;
+        TuneChoice t{};
+        bool hit = false;
+        {
+            std::lock_guard<std::mutex> lock(tune_mutex());
+            auto& cache = tune_cache();
+            auto it = cache.find(key);
+            if (it != cache.end()) { t = it->second; hit = true; }
+        }
+        // a remembered winner (possibly read from a file) is used only if this context can use
+        // it; otherwise the tuner times again
+        if (hit && choice_valid(c, t, pick_path)) return finish(t);
     }
-    // a remembered winner (possibly read from a file) is used only if it names a path this
-    // context can run and one of the candidate row counts; otherwise the tuner times again
-    if (cached >= 0) {
-        const int path = cached / 1000, rows = cached % 1000;
-        const bool path_ok = path == MPR_SWEEP_FUSED || (path == MPR_SWEEP_SPARSE && sparse_possible(c)) ||
-                             (path == MPR_SWEEP_TILED && tiled_possible(c));
-        const bool rows_ok = std::find(std::begin(kRowCandidates), std::end(kRowCandidates), rows) !=
-                             std::end(kRowCandidates);
-        if (path_ok && rows_ok && (pick_path || path == current_path(c))) return finish(path, rows);
+    if (!pick_path && c->sparse) {       // nothing to tune on the compacted path but the graphs
+        if (best_out) *best_out = c->rows;
+        if (!tune_graphs(c)) return MPR_OK;
     }
 
     int maxH = 0;
@@ -2174,6 +2243,10 @@ static int autotune(mpr_ctx* c, int n, int* best_out)
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
+    auto restore = [&]() -> int {
+        HIPCHK(c, hipMemcpyAsync(c->d_state[c->cur], saved, c->plane_elems * c->elem, hipMemcpyDeviceToDevice, c->stream));
+        return MPR_OK;
+    };
     // one candidate: n sweeps after a warm-up one, then the saved state back
     auto time_sweeps = [&](float& ms) -> int {
         int buf = c->cur;
@@ -2184,14 +2257,40 @@ static int autotune(mpr_ctx* c, int n, int* best_out)
         HIPCHK(c, hipEventRecord(e1, c->stream));
         HIPCHK(c, hipEventSynchronize(e1));
         HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-        HIPCHK(c, hipMemcpyAsync(c->d_state[c->cur], saved, c->plane_elems * c->elem, hipMemcpyDeviceToDevice, c->stream));
-        return MPR_OK;
+        return restore();
     };
-    int best_path = current_path(c), best_rows = c->rows;
+    // one graph length: a graph of K sweeps captured and replayed until about 4 n sweeps ran;
+    // time per sweep
+    auto time_graph = [&](int K, float& ms_per_sweep) -> int {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        int buf = c->cur;
+        for (int i = 0; i < K; ++i) { enqueue_sweep(c, F_ENERGY, i, buf, c->d_run, nullptr); buf ^= flips(c); }
+        HIPCHK(c, hipStreamEndCapture(c->stream, &graph));
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(c, ei);
+        const int reps = std::max(1, (4 * n + K - 1) / K);
+        hipError_t e = hipGraphLaunch(exec, c->stream);                      // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(exec, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        (void)hipGraphExecDestroy(exec);
+        HIPCHK(c, e);
+        ms_per_sweep = ms / (float)(reps * K);
+        return restore();
+    };
+    // the other paths keep the rows per work item the context had (they do not use them)
+    const int rows0 = c->rows;
+    TuneChoice best{current_path(c), rows0, c->tile_shape_req, 0};
     float best_ms = 1e30f;
     int rc = MPR_OK;
     // fused path: the six best row counts of the cost model
-    if (pick_path || best_path == MPR_SWEEP_FUSED) {
+    if (pick_path || best.path == MPR_SWEEP_FUSED) {
         std::vector<std::pair<double, int>> ranked;
         for (int r : kRowCandidates) {
             if (r > maxH && r > 2) break;
@@ -2204,17 +2303,41 @@ static int autotune(mpr_ctx* c, int n, int* best_out)
             float ms = 0.0f;
             rc = use_rows(c, ranked[k].second);
             if (!rc) rc = time_sweeps(ms);
-            if (!rc && ms < best_ms) { best_ms = ms; best_path = MPR_SWEEP_FUSED; best_rows = ranked[k].second; }
+            if (!rc && ms < best_ms) { best_ms = ms; best = {MPR_SWEEP_FUSED, ranked[k].second, -1, 0}; }
         }
     }
-    if (pick_path) {
-        for (int path : {MPR_SWEEP_SPARSE, MPR_SWEEP_TILED}) {
-            if (rc) break;
-            if (path == MPR_SWEEP_SPARSE ? !sparse_possible(c) : !tiled_possible(c)) continue;
+    if (!rc && (pick_path || best.path == MPR_SWEEP_SPARSE) && sparse_possible(c)) {
+        float ms = 0.0f;
+        rc = apply_path(c, MPR_SWEEP_SPARSE);
+        if (!rc) rc = time_sweeps(ms);
+        if (!rc && ms < best_ms) { best_ms = ms; best = {MPR_SWEEP_SPARSE, rows0, -1, 0}; }
+    }
+    if (!rc && (pick_path || best.path == MPR_SWEEP_TILED) && tiled_possible(c)) {
+        // the block shapes (one with double-precision functions, or the forced one)
+        std::vector<int> shapes;
+        if (!pick_shape) shapes.push_back(c->cfg.tile_shape - 1);
+        else if (!c->fsingle) shapes.push_back(kShapeW4Base);
+        else shapes = {kShapeW4Base, kShapeW8Tall, kShapeW4Tall, kShapeW8Base};
+        for (size_t k = 0; k < shapes.size() && !rc; ++k) {
             float ms = 0.0f;
-            rc = apply_path(c, path);
+            c->tile_shape_req = shapes[k];
+            for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+            c->graphs.clear();
+            rc = apply_path(c, MPR_SWEEP_TILED);
             if (!rc) rc = time_sweeps(ms);
-            if (!rc && ms < best_ms) { best_ms = ms; best_path = path; }
+            if (!rc && ms < best_ms) { best_ms = ms; best = {MPR_SWEEP_TILED, rows0, pick_shape ? shapes[k] : -1, 0}; }
+        }
+        c->tile_shape_req = pick_shape ? -1 : c->cfg.tile_shape - 1;
+    }
+    // sweeps per graph, on the winning path
+    if (!rc && tune_graphs(c)) {
+        rc = finish(best);
+        float best_g = 1e30f;
+        for (int K : kGraphCandidates) {
+            if (rc) break;
+            float ms = 0.0f;
+            rc = time_graph(K, ms);
+            if (!rc && ms < best_g) { best_g = ms; best.graph_k = K; }
         }
     }
     (void)hipStreamSynchronize(c->stream);
@@ -2225,12 +2348,15 @@ static int autotune(mpr_ctx* c, int n, int* best_out)
     {
         std::lock_guard<std::mutex> lock(tune_mutex());
         auto& cache = tune_cache();
-        cache[key] = best_path * 1000 + best_rows;
+        cache[key] = best;
         if (const char* path = std::getenv("MPR_TUNE_CACHE")) {
-            if (FILE* f = std::fopen(path, "a")) { std::fprintf(f, "%s %d\n", key.c_str(), cache[key]); std::fclose(f); }
+            if (FILE* f = std::fopen(path, "a")) {
+                std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), best.path, best.rows, best.shape, best.graph_k);
+                std::fclose(f);
+            }
         }
     }
-    return finish(best_path, best_rows);
+    return finish(best);
 }
 
 int mpr_autotune(mpr_ctx* c, int32_t n_sweeps, int32_t* rows_out)
@@ -2243,6 +2369,17 @@ int mpr_autotune(mpr_ctx* c, int32_t n_sweeps, int32_t* rows_out)
     rc = autotune(c, n_sweeps, &best);
     if (rows_out) *rows_out = best;
     return rc;
+}
+
+int mpr_get_tuning(mpr_ctx* c, int32_t* path, int32_t* rows, int32_t* tile_shape, int32_t* graph_sweeps)
+{
+    if (!c) return MPR_EINVAL;
+    if (c->phase < PH_LOADED) return fail(c, MPR_ESTATE, "no data loaded");
+    if (path) *path = current_path(c);
+    if (rows) *rows = c->rows;
+    if (tile_shape) *tile_shape = c->tiled ? c->tile_shape : -1;
+    if (graph_sweeps) *graph_sweeps = c->graph_k;
+    return MPR_OK;
 }
 
 int mpr_get_sweep_mode(mpr_ctx* c, int32_t* mode_out)

@@ -458,9 +458,10 @@ __device__ inline void control_step(GcCtl& c, double e_sim, int64_t n_acc, const
 
 // ------------------------------------------------------------------ cross-lane shifts
 // DPP wave shifts by one lane (a plain VALU move, no LDS crossbar): from_left(v) gives lane i
-// the value of lane i-1, from_right(v) the value of lane i+1; lanes without a source get 0.
-__device__ __forceinline__ int dpp_from_left(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
-__device__ __forceinline__ int dpp_from_right(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+// the value of lane i-1, from_right(v) the value of lane i+1; lanes without a source get 0
+// (bound_ctrl, so no move initialises the destination first).
+__device__ __forceinline__ int dpp_from_left(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ int dpp_from_right(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true); }
 __device__ __forceinline__ float from_left(float v) { return __int_as_float(dpp_from_left(__float_as_int(v))); }
 __device__ __forceinline__ float from_right(float v) { return __int_as_float(dpp_from_right(__float_as_int(v))); }
 __device__ __forceinline__ double from_left(double v)
@@ -660,18 +661,19 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
     // existence of member m at row parity p (= (y + c) & 1), rows aside: bit 2 m + p of ex_bits
     // (a value, not four addressable flags, so selecting one never goes through memory)
     const int ex_bits = lane_ok ? ((0 < wl) ? 1 : 0) | ((1 < wl) ? 2 : 0) | ((2 < wl) ? 4 : 0) | ((3 < wl) ? 8 : 0) : 0;
-    auto exists = [=](int y, int c, int m) -> bool {
-        return (((ex_bits >> (2 * m + ((y + c) & 1))) & 1) != 0) & row_ok(y);
+    // (par = (y + c) & 1 is passed by the caller: in the unrolled steady state it is a constant)
+    auto exists = [=](int y, int par, int m) -> bool {
+        return (((ex_bits >> (2 * m + par)) & 1) != 0) & row_ok(y);
     };
     auto load_pair = [&](int c, int y) -> Pair {
         const uint32_t off = (lane_ok & row_ok(y)) ? (uint32_t)(c * plane_sz + wrap(y) * pitch + col) * kRaw : kBufOOB;
         return buf_load_pair<St>(rs, off);
     };
-    auto cs_of = [&](Pair p, int y, int c) -> RowCS<F> {
+    auto cs_of = [&](Pair p, int y, int par) -> RowCS<F> {
         RowCS<F> r;
         F s, co;
         M::sincos_rev(q * St::template value<F>(p.a), s, co);
-        const bool e0 = exists(y, c, 0), e1 = exists(y, c, 1);
+        const bool e0 = exists(y, par, 0), e1 = exists(y, par, 1);
         r.c0 = e0 ? co : (F)0;
         r.s0 = e0 ? s : (F)0;
         M::sincos_rev(q * St::template value<F>(p.b), s, co);
@@ -684,11 +686,10 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
     // dn; returns the new raw pair, the (cos, sin) of the new values (zero for absent sites),
     // the decisions, and the energy of this row's colour-c bonds with their final values
     auto update_row = [&](Pair old, const RowCS<F>& up, const RowCS<F>& mid, const RowCS<F>& dn,
-                          int y, int c, Pair& nw, RowCS<F>& ncs, int& da, int& db, F& e) {
-        // horizontal neighbours: o == 0 -> member 0 uses (left lane's member 1, own member 0),
-        // member 1 uses (own 0, own 1); o == 1 -> member 0 uses (own 0, own 1), member 1 uses
-        // (own 1, right lane's member 0)
-        const int o = (y + c) & 1;
+                          int y, int c, int o, Pair& nw, RowCS<F>& ncs, int& da, int& db, F& e) {
+        // horizontal neighbours (o = (y + c) & 1, the row parity): o == 0 -> member 0 uses (left
+        // lane's member 1, own member 0), member 1 uses (own 0, own 1); o == 1 -> member 0 uses
+        // (own 0, own 1), member 1 uses (own 1, right lane's member 0)
         F C0, S0, C1, S1;
         if (o == 0) {
             const F hc = from_left(mid.c1), hs = from_left(mid.s1);
@@ -703,7 +704,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
             C1 = (mid.c1 + hc) + (up.c1 + dn.c1);
             S1 = (mid.s1 + hs) + (up.s1 + dn.s1);
         }
-        const bool ex0 = exists(y, c, 0), ex1 = exists(y, c, 1);
+        const bool ex0 = exists(y, o, 0), ex1 = exists(y, o, 1);
         const bool fr0 = ex0 & !St::sample(old.a);
         const bool fr1 = ex1 & !St::sample(old.b);
         const U4 r = philox10(U4{(uint32_t)(wrap(y) * np + jj), sweep, (uint32_t)g.chain_word,
@@ -736,7 +737,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
 
     // stores row y of both colours (new colour-0 pair n0 with its decisions, new colour-1 pair
     // n1) and accumulates the per-row outputs
-    auto finish_row = [&](int y, const Pair& n0, int d0a, int d0b, const Pair& n1, int d1a,
+    auto finish_row = [&](int y, int par, const Pair& n0, int d0a, int d0b, const Pair& n1, int d1a,
                           int d1b, F e) {
         // non-output lanes address past the resources: their stores are dropped
         const uint32_t r0 = (uint32_t)(y * pitch + col);
@@ -752,10 +753,10 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
         if (FLAGS & F_ACC) {
             const Rsrc ra = make_rsrc(a.acc + it.plane_off, gc_elems * 8u);
             const uint32_t o0 = out_lane ? r0 * 8u : kBufOOB, o1 = out_lane ? r1 * 8u : kBufOOB;
-            const bool f0a = exists(y, 0, 0) & !St::sample(n0.a);
-            const bool f0b = exists(y, 0, 1) & !St::sample(n0.b);
-            const bool f1a = exists(y, 1, 0) & !St::sample(n1.a);
-            const bool f1b = exists(y, 1, 1) & !St::sample(n1.b);
+            const bool f0a = exists(y, par, 0) & !St::sample(n0.a);
+            const bool f0b = exists(y, par, 1) & !St::sample(n0.b);
+            const bool f1a = exists(y, par ^ 1, 0) & !St::sample(n1.a);
+            const bool f1b = exists(y, par ^ 1, 1) & !St::sample(n1.b);
             double2 p0 = buf_load_f64x2(ra, o0);
             double2 p1 = buf_load_f64x2(ra, o1);
             if (f0a) p0.x += St::template value<double>(n0.a);
@@ -769,10 +770,10 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
             uint8_t* d = a.dec + g.site_off + (int64_t)y * g.W;
             const int xb = 4 * jj;
             const int o0 = y & 1, o1 = (y + 1) & 1;
-            if (exists(y, 0, 0)) d[xb + o0] = (uint8_t)d0a;
-            if (exists(y, 0, 1)) d[xb + 2 + o0] = (uint8_t)d0b;
-            if (exists(y, 1, 0)) d[xb + o1] = (uint8_t)d1a;
-            if (exists(y, 1, 1)) d[xb + 2 + o1] = (uint8_t)d1b;
+            if (exists(y, par, 0)) d[xb + o0] = (uint8_t)d0a;
+            if (exists(y, par, 1)) d[xb + 2 + o0] = (uint8_t)d0b;
+            if (exists(y, par ^ 1, 0)) d[xb + o1] = (uint8_t)d1a;
+            if (exists(y, par ^ 1, 1)) d[xb + 2 + o1] = (uint8_t)d1b;
         }
     };
 
@@ -789,9 +790,9 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
     int d0_m2a, d0_m2b, d0_m1a = 0, d0_m1b = 0, d0_0a = 0, d0_0b = 0;
 
     r1_0 = load_pair(1, ya - 2);
-    w1_0 = cs_of(r1_0, ya - 2, 1);
+    w1_0 = cs_of(r1_0, ya - 2, (ya - 1) & 1);
     r1_p1 = load_pair(1, ya - 1);
-    w1_p1 = cs_of(r1_p1, ya - 1, 1);
+    w1_p1 = cs_of(r1_p1, ya - 1, ya & 1);
     v0_next = load_pair(0, ya - 1);
     Pair pf1[kPrefetchRows], pf0[kPrefetchRows];
 #pragma unroll
@@ -800,7 +801,9 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
         pf0[d] = load_ahead(0, ya + d);
     }
 
-    auto step = [&](int k, bool c0_rows_checked, bool do_c0, bool do_c1) __attribute__((always_inline)) {
+    // par = k & 1: colour 0 at row k and colour 1 at row k + 1 have parity par, colour 1 at
+    // row k - 2 parity par ^ 1 (a constant in the unrolled steady state)
+    auto step = [&](int k, int par, bool c0_rows_checked, bool do_c0, bool do_c1) __attribute__((always_inline)) {
         w1_m1 = w1_0; w1_0 = w1_p1;
         r1_m2 = r1_m1; r1_m1 = r1_0; r1_0 = r1_p1;
         w0_m3 = w0_m2; w0_m2 = w0_m1; w0_m1 = w0_0;
@@ -816,10 +819,10 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
         }
         pf1[kPrefetchRows - 1] = load_ahead(1, k + 1 + kPrefetchRows);
         pf0[kPrefetchRows - 1] = load_ahead(0, k + 1 + kPrefetchRows);
-        if (do_c0) w1_p1 = cs_of(r1_p1, k + 1, 1);
+        if (do_c0) w1_p1 = cs_of(r1_p1, k + 1, par);
         if (do_c0 && (!c0_rows_checked || row_ok(k))) {
             F e_unused;
-            update_row(v0_cur, w1_m1, w1_0, w1_p1, k, 0, n0_0, w0_0, d0_0a, d0_0b, e_unused);
+            update_row(v0_cur, w1_m1, w1_0, w1_p1, k, 0, par, n0_0, w0_0, d0_0a, d0_0b, e_unused);
         } else {
             n0_0 = v0_cur;
             w0_0 = zero;
@@ -831,8 +834,8 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
             RowCS<F> cs1;
             int d1a, d1b;
             F e;
-            update_row(r1_m2, w0_m3, w0_m2, w0_m1, y, 1, n1, cs1, d1a, d1b, e);
-            finish_row(y, n0_m2, d0_m2a, d0_m2b, n1, d1a, d1b, e);
+            update_row(r1_m2, w0_m3, w0_m2, w0_m1, y, 1, par ^ 1, n1, cs1, d1a, d1b, e);
+            finish_row(y, par, n0_m2, d0_m2a, d0_m2b, n1, d1a, d1b, e);
         } else {
             // the same memory operations, all out of range: every path into the steady loop
             // then has the same count of stores behind the loads, and the compiler can wait for
@@ -850,9 +853,17 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
     // fill: colour 0 only (rows ya-1 ... ya+1); steady state: both colours, rows in the grid;
     // drain: colour 0 of row yb (if in the grid) and colour 1 of the last two rows
     int k = ya - 1;
-    for (; k <= ya + 1 && k <= yb; ++k) step(k, true, true, false);
-    for (; k <= yb - 1; ++k) step(k, false, true, true);
-    for (; k <= yb + 1; ++k) step(k, true, k <= yb, k - 2 >= ya);
+    for (; k <= ya + 1 && k <= yb; ++k) step(k, k & 1, true, true, false);
+    // steady state unrolled by two from an even row, so the row parities are constants (no
+    // branch on them); unrolling by four renames the windows' registers too, but its 127 VGPRs
+    // (four waves per SIMD instead of five) made the sweep 2-6 % slower
+    if (k <= yb - 1 && (k & 1)) { step(k, 1, false, true, true); ++k; }
+    for (; k + 1 <= yb - 1; k += 2) {
+        step(k, 0, false, true, true);
+        step(k + 1, 1, false, true, true);
+    }
+    for (; k <= yb - 1; ++k) step(k, k & 1, false, true, true);
+    for (; k <= yb + 1; ++k) step(k, k & 1, true, k <= yb, k - 2 >= ya);
 
     // wave reductions (inference sweeps only): exact integer sums, or a fixed-order float tree
     if (!(FLAGS & F_ENERGY)) return;

@@ -38,12 +38,18 @@ template <class S, class F> constexpr int tile_rows()
 {
     return (sizeof(typename Store<S>::raw) + 2 * sizeof(F) <= 12 || sizeof(F) == 8) ? 16 : 8;
 }
-// rows per tile of a block of NW waves: eight-wave blocks take tiles of twice the base height
-// (49-69 KB of LDS, two or three blocks per CU): on a grid that fits the chip in one round, fewer and
-// taller tiles stage and recompute less halo (10 % faster inference sweeps on 1024^2)
-template <class S, class F, int NW> constexpr int tile_rows_for()
+// Tile shapes: (waves per block, rows per tile).  The automatic rule takes eight-wave blocks on
+// tiles of twice the base height (49-69 KB of LDS, two or three blocks per CU) when a grid fits
+// the chip in about one round -- fewer and taller tiles stage and recompute less halo (10 %
+// faster inference sweeps on 1024^2) -- and four-wave blocks on base-height tiles otherwise;
+// the autotuner may pick the other two combinations (single-precision functions only: the
+// tall tiles of double-precision values would exceed the LDS of a block).
+enum { kShapeW4Base = 0, kShapeW8Tall = 1, kShapeW4Tall = 2, kShapeW8Base = 3, kTileShapes = 4 };
+constexpr int shape_waves(int shape) { return (shape == kShapeW8Tall || shape == kShapeW8Base) ? 8 : 4; }
+constexpr bool shape_tall(int shape) { return shape == kShapeW8Tall || shape == kShapeW4Tall; }
+template <class S, class F, bool TALL> constexpr int tile_rows_for()
 {
-    return NW == kTileWavesSmall ? 2 * tile_rows<S, F>() : tile_rows<S, F>();
+    return TALL ? 2 * tile_rows<S, F>() : tile_rows<S, F>();
 }
 
 struct TiledArgs {
@@ -72,14 +78,14 @@ struct TiledArgs {
 
 template <class F> struct alignas(2 * sizeof(F)) CosSin { F c, s; };
 
-template <class S, class F, int FLAGS, bool PER, int NW>
+template <class S, class F, int FLAGS, bool PER, int NW, bool TALL>
 __global__ __launch_bounds__(NW * kWave) void k_tiled(TiledArgs a)
 {
     using St = Store<S>;
     using M = Math<F>;
     using Raw = typename St::raw;
     using CS = CosSin<F>;
-    constexpr int TY = tile_rows_for<S, F, NW>(), TX = kTileCols;
+    constexpr int TY = tile_rows_for<S, F, TALL>(), TX = kTileCols;
     constexpr int R1 = TY + 4, W1 = TX + 4;       // colour-1 stage: rows y0-2 ..., columns k0-2 ...
     constexpr int R0 = TY + 2, W0 = TX + 2;       // colour-0 stage: rows y0-1 ..., columns k0-1 ...
     constexpr int N1 = R1 * W1, N0 = R0 * W0;

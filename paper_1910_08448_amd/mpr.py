@@ -18,6 +18,7 @@ PREC_DEFAULT, PREC_DOUBLE, PREC_SINGLE = -1, 0, 1
 OPEN, PERIODIC = 0, 1
 DEC_OR, DEC_ACCEPT, DEC_OUTSIDE = 1, 2, 4
 SWEEP_AUTO, SWEEP_FUSED, SWEEP_SPARSE, SWEEP_TILED = 0, 1, 2, 3
+TILE_W4_BASE, TILE_W8_TALL, TILE_W4_TALL, TILE_W8_BASE = 0, 1, 2, 3
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libmpr.so is not built (%s); run paper_1910_08448_amd/build.py" % LIB_PATH)
@@ -33,7 +34,7 @@ class mpr_config(ctypes.Structure):
                 ("acc_target", ctypes.c_double), ("T_min", ctypes.c_double),
                 ("T_max", ctypes.c_double), ("tile_rows", ctypes.c_int32),
                 ("graph_sweeps", ctypes.c_int32), ("sweep_mode", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("tile_shape", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class mpr_chain_stats(ctypes.Structure):
@@ -70,6 +71,7 @@ _SIG = {
     "mpr_autotune": (ctypes.c_int, [_vp, _i32, _vp]),
     "mpr_get_shape": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "mpr_get_sweep_mode": (ctypes.c_int, [_vp, _vp]),
+    "mpr_get_tuning": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "mpr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "mpr_last_error": (ctypes.c_char_p, [_vp]),
 }
@@ -188,6 +190,13 @@ class Context:
         m = ctypes.c_int32()
         self._chk(_lib.mpr_get_sweep_mode(self.h, ctypes.byref(m)), "mpr_get_sweep_mode")
         return m.value
+
+    def tuning(self):
+        """(sweep path, fused rows per work item, tiled block shape or -1, sweeps per graph or -1)
+        the context sweeps with."""
+        v = [ctypes.c_int32() for _ in range(4)]
+        self._chk(_lib.mpr_get_tuning(self.h, *[ctypes.byref(x) for x in v]), "mpr_get_tuning")
+        return tuple(x.value for x in v)
 
     def load(self, z, mask):
         """z: float64 CUDA tensor [H, W]; mask: uint8 CUDA tensor [H, W]."""

@@ -185,11 +185,13 @@ def test_fp64_predictions_match_oracle_grid64(mpr, p):
 def test_predictions_invariant_to_tiles_and_graphs(mpr, mode):
     w = synth.workload("grid64")
     res = []
-    for tile_rows, graph in [(16, 0), (64, 0), (16, -1), (8, 4)]:
+    # graphs of 6 and 64 sweeps leave remainders (odd ones: 41 = 6 * 6 + 5) that run as graphs
+    # of their own length
+    for tile_rows, graph in [(16, 0), (64, 0), (16, -1), (8, 4), (8, 6), (8, 64)]:
         ctx = _gpu_ctx(mpr, w["z"], w["mask"], seed=3, precision=mpr.FP32, tile_rows=tile_rows,
                        graph_sweeps=graph, n_chains=2, sweep_mode=mode)
-        ctx.infer_temperature(40)
-        ctx.run(10)
+        ctx.infer_temperature(41)
+        ctx.run(11)
         res.append(ctx.predictions().cpu().numpy())
     for r in res[1:]:
         assert np.array_equal(r, res[0])
@@ -665,16 +667,22 @@ def test_autotuned_path_reproduces_the_chosen_path(mpr, precision):
     kw = dict(seed=5, precision=precision, n_chains=2)
     tuned = _gpu_ctx(mpr, w["z"], w["mask"], tile_rows=-1, **kw)
     mode = tuned.sweep_mode()
-    assert mode in (mpr.SWEEP_FUSED, mpr.SWEEP_SPARSE, mpr.SWEEP_TILED)
+    path, rows, shape, gk = tuned.tuning()
+    assert mode == path and mode in (mpr.SWEEP_FUSED, mpr.SWEEP_SPARSE, mpr.SWEEP_TILED)
+    assert gk in (16, 32, 64)
+    assert (shape in range(4)) == (mode == mpr.SWEEP_TILED)
     Tt = tuned.infer_temperature(30)
     tuned.run(10)
-    forced = _gpu_ctx(mpr, w["z"], w["mask"], sweep_mode=mode, **kw)
+    # the same configuration forced: path, rows per work item, tile shape, graph length
+    forced = _gpu_ctx(mpr, w["z"], w["mask"], sweep_mode=mode, tile_rows=rows, graph_sweeps=gk,
+                      tile_shape=shape + 1 if shape >= 0 else 0, **kw)
+    assert forced.tuning() == (path, rows, shape, gk)
     Tf = forced.infer_temperature(30)
     forced.run(10)
     assert np.array_equal(Tt, Tf)
     assert np.array_equal(tuned.predictions().cpu().numpy(), forced.predictions().cpu().numpy())
     again = _gpu_ctx(mpr, w["z"], w["mask"], tile_rows=-1, **kw)
-    assert again.sweep_mode() == mode
+    assert again.tuning() == (path, rows, shape, gk)
 
 
 @pytest.mark.parametrize("precision", [1, 2])
@@ -784,3 +792,31 @@ def test_binding_refuses_buffers_the_kernels_cannot_use(mpr):
         ctx.load(_dev(z, torch.float32), _dev(mask, torch.uint8))
     out = ctx.predictions(out=torch.empty(n, dtype=torch.float64, device="cuda"))
     assert np.isfinite(out.cpu().numpy()).all()
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_every_tile_shape_equals_sparse(mpr, precision):
+    """The tiled path's four block shapes (four or eight waves, base or double tile height) run
+    a batch of uneven grids with two chains bit for bit like the compacted path; with
+    double-precision functions only the four-wave base shape exists."""
+    shapes = [(45, 70), (130, 300), (66, 264), (2, 3)]
+    fields = [_field(h, w, 700 + i) for i, (h, w) in enumerate(shapes)]
+    z = np.concatenate([f[1].ravel() for f in fields])
+    m = np.concatenate([f[2].ravel() for f in fields])
+
+    def run(**cfg):
+        ctx = mpr.Context(shapes=shapes, stream=torch.cuda.Stream(), seed=8, n_chains=2,
+                          precision=precision, **cfg)
+        ctx.batch_load(_dev(z, torch.float64), _dev(m, torch.uint8))
+        T = ctx.infer_temperature(20)
+        tr = ctx.trace(3)
+        ctx.run(6)
+        return ctx.tuning(), T, tr, ctx.predictions().cpu().numpy()
+
+    ref = run(sweep_mode=mpr.SWEEP_SPARSE)
+    for shape in range(4):
+        tun, T, tr, zh = run(sweep_mode=mpr.SWEEP_TILED, tile_shape=shape + 1)
+        assert tun[0] == mpr.SWEEP_TILED and tun[2] == shape
+        assert np.array_equal(T, ref[1]) and np.array_equal(tr, ref[2]) and np.array_equal(zh, ref[3])
+    with pytest.raises(mpr.MprError):
+        mpr.Context(precision=mpr.FP32, func_prec=mpr.PREC_DOUBLE, tile_shape=mpr.TILE_W8_TALL + 1)
