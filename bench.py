@@ -154,15 +154,22 @@ def oracle_subset(name):
 SWEEP_MODE = {"auto": 0, "fused": 1, "sparse": 2, "tiled": 3}
 
 
-def measure(inp, precision, steps, warmup, kernel_launches, torch, M, sweep_mode="auto"):
+def measure(inp, precision, steps, warmup, kernel_launches, torch, M, sweep_mode="auto", autotune=True):
     chains = CHAINS.get(inp.name, 1)
     n_equil, n_avg = SWEEPS[inp.name]
     P = sum(inp.n_pred) * chains
     updates_per_step = P * (n_equil + n_avg)
     stream = torch.cuda.Stream()
+    # tile_rows = -1: the library's autotuner picks the sweep path, the fused path's rows per work
+    # item, the tiled path's block shape and the sweeps per captured graph at the first load (a
+    # warm-up step); later loads of the same shapes take the remembered choice
     ctx = M.Context(shapes=inp.shapes, stream=stream, precision=PREC[precision], n_chains=chains,
-                    seed=inp.mc_seed, sweep_mode=SWEEP_MODE[sweep_mode])
+                    seed=inp.mc_seed, sweep_mode=SWEEP_MODE[sweep_mode],
+                    tile_rows=-1 if autotune else 0)
     zhat = torch.empty(sum(inp.n_sites), dtype=torch.float64, device="cuda")
+    # set-up (not a step): a first load, where the autotuner times its candidates once
+    with torch.cuda.stream(stream):
+        ctx.batch_load(inp.z, inp.m)
     torch.cuda.synchronize()
 
     # HIP events on the library's stream around each timed step's inference sweeps: the
@@ -213,6 +220,7 @@ def measure(inp, precision, steps, warmup, kernel_launches, torch, M, sweep_mode
             abs_sub += float(np.abs(err).sum())
             n_sub += err.size
     mae, rmse = abs_all / n_all, float(np.sqrt(sq_all / n_all))
+    phases = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in ctx.timings().items()}
     stats = ctx.stats()
     T_hat = [s["T"] for s in stats]
     clamped = sum(1 for t in T_hat if t <= T_MIN * (1 + 1e-12) or t >= T_MAX * (1 - 1e-12))
@@ -231,7 +239,11 @@ def measure(inp, precision, steps, warmup, kernel_launches, torch, M, sweep_mode
     kernel_ms_b2b = ev0.elapsed_time(ev1) / kernel_launches
     if kernel_ms is None:
         kernel_ms = kernel_ms_b2b
-    path = {M.SWEEP_SPARSE: "sparse", M.SWEEP_TILED: "tiled"}.get(ctx.sweep_mode(), "fused")
+    tun = ctx.tuning()
+    path = {M.SWEEP_SPARSE: "sparse", M.SWEEP_TILED: "tiled"}.get(tun[0], "fused")
+    tuning = {"autotuned": autotune, "path": path, "rows_per_item": tun[1],
+              "tile_shape": ["w4_base", "w8_tall", "w4_tall", "w8_base"][tun[2]] if tun[2] >= 0 else None,
+              "graph_sweeps": tun[3]}
     kernel_name = {"sparse": "k_sparse<colour 0> + k_sparse<colour 1> (inference variant, one sweep)",
                    "tiled": "k_tiled (inference variant)"}.get(path, "k_sweep (inference variant)")
     s = BYTES[precision]
@@ -253,9 +265,10 @@ def measure(inp, precision, steps, warmup, kernel_launches, torch, M, sweep_mode
     out = {"workload": inp.name, "precision": precision, "value": value,
            "unit": "site-updates/s", "ms_per_step": ms_per_step, "steps": steps,
            "grids": len(inp.shapes), "sites": sum(inp.n_sites), "prediction_sites": sum(inp.n_pred),
-           "chains": chains, "sweep_path": path, "n_equil": n_equil, "n_avg": n_avg,
+           "chains": chains, "sweep_path": path, "tuning": tuning, "n_equil": n_equil, "n_avg": n_avg,
            "lattice_site_rate": lattice_rate, "mae": mae, "rmse": rmse,
-           "T_hat": T_hat[:4], "T_hat_clamped": clamped, "roofline": roofline}
+           "T_hat": T_hat[:4], "T_hat_clamped": clamped, "phase_ms_last_step": phases,
+           "roofline": roofline}
     ref = oracle_reference(inp.name, inp.p_missing)
     if ref is not None and chains == ref["chains"]:
         out["oracle_mae"] = ref["mae"]
@@ -348,6 +361,8 @@ def main():
     ap.add_argument("--sweep-mode", default="auto", choices=sorted(SWEEP_MODE),
                     help="sweep path: automatic choice, fused row blocks, compacted site lists, or LDS tiles")
     ap.add_argument("--kernel-launches", type=int, default=20)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="the library's automatic rule instead of its autotuner")
     ap.add_argument("--setup-steps", type=int, default=3, help="timed steps of each secondary setup")
     ap.add_argument("--cpu-seconds", type=float, default=8.0,
                     help="oracle time per CPU-baseline run (all cores, then one core)")
@@ -380,7 +395,7 @@ def main():
     copy_gbs = streaming_copy_gbs(torch) if args.copy_probe_mib <= 0 else None
     inputs = {args.workload: Inputs(args.workload, args.p_missing, torch)}
     prim = measure(inputs[args.workload], args.precision, args.steps, args.warmup,
-                   args.kernel_launches, torch, M, args.sweep_mode)
+                   args.kernel_launches, torch, M, args.sweep_mode, not args.no_autotune)
 
     setups = []
     if not args.no_setups:
@@ -397,7 +412,7 @@ def main():
                 inputs[wl] = Inputs(wl, None, torch)
             steps = max(1, min(args.steps, args.setup_steps))
             setups.append(measure(inputs[wl], prec, steps, 1, args.kernel_launches, torch, M,
-                                  args.sweep_mode))
+                                  args.sweep_mode, not args.no_autotune))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -414,7 +429,7 @@ def main():
                    "grids": prim["grids"], "sites": prim["sites"],
                    "prediction_sites": prim["prediction_sites"], "chains": prim["chains"],
                    "n_equil": prim["n_equil"], "n_avg": prim["n_avg"],
-                   "sweep_path": prim["sweep_path"]},
+                   "sweep_path": prim["sweep_path"], "tuning": prim["tuning"]},
         "fp64_factor": (prim["value"] / fp64["value"]) if fp64 else None,
         "mae": prim["mae"], "rmse": prim["rmse"], "T_hat": prim["T_hat"],
         "T_hat_clamped": prim["T_hat_clamped"],

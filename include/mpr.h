@@ -239,6 +239,17 @@ typedef struct mpr_chain_stats {
 /* out_host[n_grids * n_chains]; synchronises. */
 int mpr_get_stats(mpr_ctx* ctx, mpr_chain_stats* out_host);
 
+/* Stream time of the last call of each phase, in milliseconds, from events the library records
+ * on its stream before the call's first and after its last enqueued work (so it includes any
+ * time the stream waited in between): the last load (with the autotuner's timing if it ran),
+ * the last inference or equilibration, the last averaging run, the last predictions; -1 for a
+ * phase not run yet.  infer_sweeps / run_sweeps: the sweeps of those calls.  Synchronises. */
+typedef struct mpr_timings {
+    double load_ms, infer_ms, run_ms, predict_ms;
+    int64_t infer_sweeps, run_sweeps;
+} mpr_timings;
+int mpr_get_timings(mpr_ctx* ctx, mpr_timings* out_host);
+
 /* Per-sweep record of the last inference of chain `grid_chain` (= g * n_chains + chain):
  * out_host[max_entries][4] = (e_sim, T, alpha, acceptance) of each sweep; *n_out entries. */
 int mpr_get_trace(mpr_ctx* ctx, int32_t grid_chain, int32_t max_entries, double* out_host,

@@ -775,6 +775,11 @@ struct mpr_ctx {
     int tile_shape = kShapeW4Base;   // (waves per block, tile height) of the tiled path
     int tile_shape_req = -1;         // shape asked for: forced by the configuration or picked by
                                      // the autotuner; -1 = the automatic rule
+    // stream time of the last call of each phase (load, inference / equilibration, averaging,
+    // predictions): events recorded before its first and after its last enqueued work
+    hipEvent_t ev[4][2] = {};
+    bool ev_done[4] = {};
+    int64_t ev_sweeps[4] = {};
 };
 
 static const char* kStatusText[] = {
@@ -1376,7 +1381,23 @@ void mpr_destroy(mpr_ctx* c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     free_device(c);
+    for (auto& pair : c->ev)
+        for (hipEvent_t e : pair)
+            if (e) (void)hipEventDestroy(e);
     delete c;
+}
+
+enum { PHASE_LOAD = 0, PHASE_INFER = 1, PHASE_RUN = 2, PHASE_PREDICT = 3 };
+
+// records the start (end = 0) or the end (end = 1) of a phase on the context's stream
+static int mark(mpr_ctx* c, int phase, int end, int64_t sweeps = 0)
+{
+    hipEvent_t& e = c->ev[phase][end];
+    if (!e) HIPCHK(c, hipEventCreate(&e));
+    HIPCHK(c, hipEventRecord(e, c->stream));
+    if (end) { c->ev_done[phase] = true; c->ev_sweeps[phase] = sweeps; }
+    else c->ev_done[phase] = false;
+    return MPR_OK;
 }
 
 static int usable(mpr_ctx* c)
@@ -1392,6 +1413,8 @@ static int autotune(mpr_ctx* c, int n, int* best_out);
 static int load_common(mpr_ctx* c, const double* z, const uint8_t* mask, bool free_only = false)
 {
     int rc = alloc_device(c);
+    if (rc) return rc;
+    rc = mark(c, PHASE_LOAD, 0);
     if (rc) return rc;
     c->gi.assign(c->G, GridInfo{});
     int64_t max_sites = 0;
@@ -1450,8 +1473,11 @@ static int load_common(mpr_ctx* c, const double* z, const uint8_t* mask, bool fr
     int prc = choose_path(c);
     if (prc) return prc;
     c->phase = PH_LOADED;
-    if (c->cfg.tile_rows == -1) return autotune(c, 8, nullptr);
-    return MPR_OK;
+    if (c->cfg.tile_rows == -1) {
+        const int trc = autotune(c, 8, nullptr);
+        if (trc) return trc;
+    }
+    return mark(c, PHASE_LOAD, 1);
 }
 
 int mpr_load(mpr_ctx* c, int64_t H, int64_t W, const double* z, const uint8_t* mask)
@@ -1722,6 +1748,8 @@ static int infer_common(mpr_ctx* c, int32_t n_equil, int fixed, double* T_host)
         for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);   // captured trace pointer
         c->graphs.clear();
     }
+    rc = mark(c, PHASE_INFER, 0);
+    if (rc) return rc;
     hipLaunchKernelGGL(k_infer_begin, dim3((3 * n_gc * kAccCopies + 255) / 256), dim3(256), 0, c->stream, c->d_ctl,
                        c->d_ictl, c->d_gacc, (c->sparse || c->tiled) ? c->d_econst : nullptr, n_gc, c->cfg.J,
                        c->cfg.T_min, c->cfg.T_max, c->d_run,
@@ -1733,6 +1761,8 @@ static int infer_common(mpr_ctx* c, int32_t n_equil, int fixed, double* T_host)
                        c->d_ctl, c->d_ictl, c->d_gacc, c->d_trace, c->d_run, n_gc, (int)!c->esingle,
                        (int64_t)n_equil, c->cfg.J, c->cfg.acc_target, c->cfg.T_min, c->cfg.T_max);
     HIPCHK(c, hipGetLastError());
+    rc = mark(c, PHASE_INFER, 1, n_equil);
+    if (rc) return rc;
     c->trace_len = n_equil;
     c->phase = std::max(c->phase, (int)PH_TEMPERED);
     if (T_host) {
@@ -1929,7 +1959,9 @@ int mpr_run(mpr_ctx* c, int32_t n_avg)
     if (rc) return rc;
     if (n_avg < 0) return fail(c, MPR_EINVAL, "n_avg < 0");
     if (c->phase < PH_TEMPERED) return fail(c, MPR_ESTATE, "no temperature: infer or set it first");
-    rc = run_sweeps(c, MODE_AVG, n_avg);
+    rc = mark(c, PHASE_RUN, 0);
+    if (!rc) rc = run_sweeps(c, MODE_AVG, n_avg);
+    if (!rc) rc = mark(c, PHASE_RUN, 1, n_avg);
     if (rc) return rc;
     c->n_avg += n_avg;
     if (n_avg > 0) c->phase = PH_AVERAGED;
@@ -1945,6 +1977,8 @@ int mpr_get_predictions(mpr_ctx* c, double* zhat)
     int64_t max_sites = 0;
     for (int g = 0; g < c->G; ++g) max_sites = std::max(max_sites, c->H[g] * c->W[g]);
     const dim3 grid = site_grid(max_sites, c->G);
+    rc = mark(c, PHASE_PREDICT, 0);
+    if (rc) return rc;
     switch (c->sprec) {
     case MPR_FP64: hipLaunchKernelGGL(k_finalize<double>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_gi, c->d_state[c->cur], c->d_acc, c->d_zcopy, zhat, c->C, c->n_avg); break;
     case MPR_FP32: hipLaunchKernelGGL(k_finalize<float>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_gi, c->d_state[c->cur], c->d_acc, c->d_zcopy, zhat, c->C, c->n_avg); break;
@@ -1952,6 +1986,23 @@ int mpr_get_predictions(mpr_ctx* c, double* zhat)
     default: hipLaunchKernelGGL(k_finalize<_Float16>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_gi, c->d_state[c->cur], c->d_acc, c->d_zcopy, zhat, c->C, c->n_avg); break;
     }
     HIPCHK(c, hipGetLastError());
+    return mark(c, PHASE_PREDICT, 1);
+}
+
+int mpr_get_timings(mpr_ctx* c, mpr_timings* out)
+{
+    if (!c || !out) return MPR_EINVAL;
+    double* ms[4] = {&out->load_ms, &out->infer_ms, &out->run_ms, &out->predict_ms};
+    for (int p = 0; p < 4; ++p) {
+        *ms[p] = -1.0;
+        if (!c->ev_done[p]) continue;
+        HIPCHK(c, hipEventSynchronize(c->ev[p][1]));
+        float t = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&t, c->ev[p][0], c->ev[p][1]));
+        *ms[p] = t;
+    }
+    out->infer_sweeps = c->ev_done[PHASE_INFER] ? c->ev_sweeps[PHASE_INFER] : 0;
+    out->run_sweeps = c->ev_done[PHASE_RUN] ? c->ev_sweeps[PHASE_RUN] : 0;
     return MPR_OK;
 }
 
@@ -2205,14 +2256,17 @@ static int autotune(mpr_ctx* c, int n, int* best_out)
     const std::string key = tune_key(c);
     auto finish = [&](const TuneChoice& t) -> int {
         int rc = MPR_OK;
-        if (t.rows != c->rows) rc = use_rows(c, t.rows);
+        const bool was_tiled = c->tiled;
+        const int old_shape = c->tile_shape;
+        if (t.rows != c->rows) rc = use_rows(c, t.rows);        // drops the graphs itself
         if (!rc && pick_shape) c->tile_shape_req = t.path == MPR_SWEEP_TILED ? t.shape : -1;
-        if (!rc) {
-            // a new tile shape changes the launches the graphs hold
+        if (!rc) rc = apply_path(c, t.path);                     // drops them on a path change
+        if (!rc && was_tiled && c->tiled && c->tile_shape != old_shape) {
+            // another tile shape changes the launches the graphs hold
             for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
             c->graphs.clear();
-            rc = apply_path(c, t.path);
         }
+        // graphs are kept per length: another length needs no drop
         if (!rc && t.graph_k > 0 && tune_graphs(c)) c->graph_k = t.graph_k;
         if (best_out) *best_out = c->rows;
         return rc;
@@ -2287,9 +2341,11 @@ static int autotune(mpr_ctx* c, int n, int* best_out)
     // the other paths keep the rows per work item the context had (they do not use them)
     const int rows0 = c->rows;
     TuneChoice best{current_path(c), rows0, c->tile_shape_req, 0};
-    float best_ms = 1e30f;
     int rc = MPR_OK;
-    // fused path: the six best row counts of the cost model
+    // the candidates: the fused path's row counts (the six best of the cost model and the rule's
+    // count), the compacted path, the tiled path's block shapes (one with double-precision
+    // functions, or the forced one)
+    std::vector<TuneChoice> cands;
     if (pick_path || best.path == MPR_SWEEP_FUSED) {
         std::vector<std::pair<double, int>> ranked;
         for (int r : kRowCandidates) {
@@ -2298,47 +2354,62 @@ static int autotune(mpr_ctx* c, int n, int* best_out)
         }
         std::sort(ranked.begin(), ranked.end());
         if (ranked.size() > 6) ranked.resize(6);
-        rc = apply_path(c, MPR_SWEEP_FUSED);
-        for (size_t k = 0; k < ranked.size() && !rc; ++k) {
-            float ms = 0.0f;
-            rc = use_rows(c, ranked[k].second);
-            if (!rc) rc = time_sweeps(ms);
-            if (!rc && ms < best_ms) { best_ms = ms; best = {MPR_SWEEP_FUSED, ranked[k].second, -1, 0}; }
-        }
+        const int rule = choose_rows(c);
+        if (std::none_of(ranked.begin(), ranked.end(), [&](const std::pair<double, int>& x) { return x.second == rule; }))
+            ranked.push_back({0.0, rule});
+        for (const auto& x : ranked) cands.push_back({MPR_SWEEP_FUSED, x.second, -1, 0});
     }
-    if (!rc && (pick_path || best.path == MPR_SWEEP_SPARSE) && sparse_possible(c)) {
-        float ms = 0.0f;
-        rc = apply_path(c, MPR_SWEEP_SPARSE);
-        if (!rc) rc = time_sweeps(ms);
-        if (!rc && ms < best_ms) { best_ms = ms; best = {MPR_SWEEP_SPARSE, rows0, -1, 0}; }
-    }
-    if (!rc && (pick_path || best.path == MPR_SWEEP_TILED) && tiled_possible(c)) {
-        // the block shapes (one with double-precision functions, or the forced one)
+    if ((pick_path || best.path == MPR_SWEEP_SPARSE) && sparse_possible(c))
+        cands.push_back({MPR_SWEEP_SPARSE, rows0, -1, 0});
+    if ((pick_path || best.path == MPR_SWEEP_TILED) && tiled_possible(c)) {
         std::vector<int> shapes;
         if (!pick_shape) shapes.push_back(c->cfg.tile_shape - 1);
         else if (!c->fsingle) shapes.push_back(kShapeW4Base);
         else shapes = {kShapeW4Base, kShapeW8Tall, kShapeW4Tall, kShapeW8Base};
-        for (size_t k = 0; k < shapes.size() && !rc; ++k) {
-            float ms = 0.0f;
-            c->tile_shape_req = shapes[k];
-            for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
-            c->graphs.clear();
-            rc = apply_path(c, MPR_SWEEP_TILED);
-            if (!rc) rc = time_sweeps(ms);
-            if (!rc && ms < best_ms) { best_ms = ms; best = {MPR_SWEEP_TILED, rows0, pick_shape ? shapes[k] : -1, 0}; }
-        }
-        c->tile_shape_req = pick_shape ? -1 : c->cfg.tile_shape - 1;
+        for (int sh : shapes) cands.push_back({MPR_SWEEP_TILED, rows0, sh, 0});
     }
+    // three interleaved rounds over the candidates, the fastest time of each counts (a first
+    // candidate timed while the clocks still ramp up would otherwise lose); large workloads time
+    // three times the sweeps (differences between candidates are a few per cent there)
+    int64_t work = 0;
+    for (int g = 0; g < c->G; ++g) work += c->H[g] * c->W[g] * c->C;
+    if (work > ((int64_t)1 << 24)) n *= 3;
+    std::vector<float> best_t(cands.size(), 1e30f);
+    for (int round = 0; round < 3 && !rc; ++round)
+        for (size_t k = 0; k < cands.size() && !rc; ++k) {
+            const TuneChoice& t = cands[k];
+            float ms = 0.0f;
+            if (t.path == MPR_SWEEP_FUSED && t.rows != c->rows) rc = use_rows(c, t.rows);
+            if (!rc && t.path == MPR_SWEEP_TILED) {
+                c->tile_shape_req = t.shape;
+                for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+                c->graphs.clear();
+            }
+            if (!rc) rc = apply_path(c, t.path);
+            if (!rc) rc = time_sweeps(ms);
+            if (!rc) best_t[k] = std::min(best_t[k], ms);
+        }
+    c->tile_shape_req = pick_shape ? -1 : c->cfg.tile_shape - 1;
+    float best_ms = 1e30f;
+    for (size_t k = 0; k < cands.size(); ++k)
+        if (best_t[k] < best_ms) {
+            best_ms = best_t[k];
+            best = cands[k];
+            if (best.path == MPR_SWEEP_TILED && !pick_shape) best.shape = -1;
+        }
     // sweeps per graph, on the winning path
     if (!rc && tune_graphs(c)) {
         rc = finish(best);
-        float best_g = 1e30f;
-        for (int K : kGraphCandidates) {
-            if (rc) break;
-            float ms = 0.0f;
-            rc = time_graph(K, ms);
-            if (!rc && ms < best_g) { best_g = ms; best.graph_k = K; }
-        }
+        float best_g[3] = {1e30f, 1e30f, 1e30f};
+        for (int round = 0; round < 2 && !rc; ++round)
+            for (int i = 0; i < 3 && !rc; ++i) {
+                float ms = 0.0f;
+                rc = time_graph(kGraphCandidates[i], ms);
+                if (!rc) best_g[i] = std::min(best_g[i], ms);
+            }
+        float bg = 1e30f;
+        for (int i = 0; i < 3; ++i)
+            if (best_g[i] < bg) { bg = best_g[i]; best.graph_k = kGraphCandidates[i]; }
     }
     (void)hipStreamSynchronize(c->stream);
     (void)hipEventDestroy(e0);

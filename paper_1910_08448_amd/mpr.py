@@ -37,6 +37,12 @@ class mpr_config(ctypes.Structure):
                 ("tile_shape", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
+class mpr_timings(ctypes.Structure):
+    _fields_ = [("load_ms", ctypes.c_double), ("infer_ms", ctypes.c_double),
+                ("run_ms", ctypes.c_double), ("predict_ms", ctypes.c_double),
+                ("infer_sweeps", ctypes.c_int64), ("run_sweeps", ctypes.c_int64)]
+
+
 class mpr_chain_stats(ctypes.Structure):
     _fields_ = [("T", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("e_sample", ctypes.c_double), ("e_sim", ctypes.c_double),
@@ -72,6 +78,7 @@ _SIG = {
     "mpr_get_shape": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "mpr_get_sweep_mode": (ctypes.c_int, [_vp, _vp]),
     "mpr_get_tuning": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "mpr_get_timings": (ctypes.c_int, [_vp, _vp]),
     "mpr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "mpr_last_error": (ctypes.c_char_p, [_vp]),
 }
@@ -190,6 +197,13 @@ class Context:
         m = ctypes.c_int32()
         self._chk(_lib.mpr_get_sweep_mode(self.h, ctypes.byref(m)), "mpr_get_sweep_mode")
         return m.value
+
+    def timings(self):
+        """Stream time (ms) of the last load, inference, averaging run and predictions, and the
+        sweeps of the last inference and run."""
+        t = mpr_timings()
+        self._chk(_lib.mpr_get_timings(self.h, ctypes.byref(t)), "mpr_get_timings")
+        return {k: getattr(t, k) for k, _ in mpr_timings._fields_}
 
     def tuning(self):
         """(sweep path, fused rows per work item, tiled block shape or -1, sweeps per graph or -1)

@@ -820,3 +820,19 @@ def test_every_tile_shape_equals_sparse(mpr, precision):
         assert np.array_equal(T, ref[1]) and np.array_equal(tr, ref[2]) and np.array_equal(zh, ref[3])
     with pytest.raises(mpr.MprError):
         mpr.Context(precision=mpr.FP32, func_prec=mpr.PREC_DOUBLE, tile_shape=mpr.TILE_W8_TALL + 1)
+
+
+def test_timings_report_each_phase(mpr):
+    """mpr_get_timings: stream time of the last load, inference, averaging run and predictions,
+    and their sweep counts; -1 for phases not run yet."""
+    truth, z, mask = _field(40, 56, 9)
+    ctx = mpr.Context(stream=torch.cuda.Stream(), precision=mpr.FP32)
+    ctx.load(_dev(z, torch.float64), _dev(mask, torch.uint8))
+    t = ctx.timings()
+    assert t["load_ms"] > 0.0 and t["infer_ms"] == -1.0 and t["run_ms"] == -1.0
+    ctx.infer_temperature(33)
+    ctx.run(7)
+    ctx.predictions()
+    t = ctx.timings()
+    assert t["infer_ms"] > 0.0 and t["run_ms"] > 0.0 and t["predict_ms"] > 0.0
+    assert t["infer_sweeps"] == 33 and t["run_sweeps"] == 7
