@@ -4,6 +4,13 @@
       kernel table (calls, average / min / max duration, share) from DIR/run_kernel_stats.csv
   python -m paper_1910_08448_amd.rocprof_summary pmc DIR [DIR ...]
       mean counter value per dispatch of the sweep kernels and of the copy probe
+  python -m paper_1910_08448_amd.rocprof_summary valu DIR UPDATES
+      VALU issue of the sweep kernels from a run with SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU,
+      SQ_ACTIVE_INST_VALU2, SQ_INSTS_VALU_TRANS_F32 and GRBM_GUI_ACTIVE: issue units (quad-cycles
+      of VALU work; a transcendental takes two) per quad-cycle per SIMD over the kernel's active
+      time -- against one (single issue) and two (the dual-issue limit) --, the share of
+      quad-cycles that issued two instructions, and lane-units and transcendentals per site
+      update (UPDATES = site updates per launch of the inference sweep)
   python -m paper_1910_08448_amd.rocprof_summary traffic KEY COPY_MIB FETCH_DIR WRITE_DIR [OUT]
       HBM bytes per launch of the inference sweep kernel: FETCH_SIZE and WRITE_SIZE (KiB per
       dispatch) each scaled by what the same counter read for the copy probe of COPY_MIB MiB
@@ -95,6 +102,36 @@ def pmc(dirs):
     return "\n".join(out)
 
 
+N_SIMD = 256 * 4          # MI355X: 256 CUs x 4 SIMDs
+N_XCD = 8                 # GRBM_GUI_ACTIVE is reported summed over the 8 XCDs
+
+
+def valu(d, updates):
+    rows = list(csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))))
+    agg = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in rows:
+        k = _infer_sweep_kind(r["Kernel_Name"])
+        if k is None:
+            if "k_sweep" in r["Kernel_Name"] or "k_tiled" in r["Kernel_Name"] or "k_sparse" in r["Kernel_Name"]:
+                k = "other sweep variant: " + r["Kernel_Name"][:60]
+            else:
+                continue
+        agg[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    out = ["| kernel | dispatches | VALU instr / dispatch | issue units / quad-cycle / SIMD | of single issue | of dual issue | dual-issued quad-cycles | lane-units / update | transcendentals / update |",
+           "|---|---|---|---|---|---|---|---|---|"]
+    for k in sorted(agg):
+        m = {c: sum(v) / len(v) for c, v in agg[k].items()}
+        n = len(agg[k].get("SQ_INSTS_VALU", []))
+        act, act2 = m.get("SQ_ACTIVE_INST_VALU", 0.0), m.get("SQ_ACTIVE_INST_VALU2", 0.0)
+        quads = m.get("GRBM_GUI_ACTIVE", 0.0) / N_XCD / 4.0
+        rate = act / (N_SIMD * quads) if quads else float("nan")
+        per_upd = act * 64.0 / updates if k in ("fused", "tiled") else float("nan")
+        tr = m.get("SQ_INSTS_VALU_TRANS_F32", 0.0) * 64.0 / updates if k in ("fused", "tiled") else float("nan")
+        out.append("| %s | %d | %.4g | %.3f | %.3f | %.3f | %.3f | %.1f | %.2f |" % (
+            k, n, m.get("SQ_INSTS_VALU", 0.0), rate, rate, rate / 2.0, act2 / act if act else 0.0, per_upd, tr))
+    return "\n".join(out)
+
+
 def traffic(fetch_dir, write_dir, copy_mib):
     """Per inference sweep: the fused kernel's dispatch, or the two colour kernels of the
     compacted path added."""
@@ -115,6 +152,12 @@ def traffic(fetch_dir, write_dir, copy_mib):
                     kinds[k].append(float(r["Counter_Value"]))
         if not kinds or len(probe) != 1:
             raise SystemExit("%s: %d sweep kernels, %d copy probes" % (d, len(kinds), len(probe)))
+        # the path the run swept with is the one with the most dispatches (an autotuner at load
+        # also launches the other paths' kernels a few times); the compacted path's sweep is
+        # its two colour kernels
+        main = max(kinds, key=lambda k: len(kinds[k]))
+        keep = ["sparse0", "sparse1"] if main.startswith("sparse") else [main]
+        kinds = {k: v for k, v in kinds.items() if k in keep}
         factor = copy_mib * 1024.0 / probe[0]          # true KiB per counted KiB
         kib = sum(sum(v) / len(v) for v in kinds.values())
         res[ctr] = {"kib_per_sweep": kib, "factor": factor, "kernels": sorted(kinds),
@@ -128,6 +171,8 @@ def main(argv):
         print(stats(argv[1]))
     elif len(argv) >= 2 and argv[0] == "pmc":
         print(pmc(argv[1:]))
+    elif len(argv) >= 3 and argv[0] == "valu":
+        print(valu(argv[1], float(argv[2])))
     elif len(argv) >= 5 and argv[0] == "traffic":
         key, copy_mib, fdir, wdir = argv[1], float(argv[2]), argv[3], argv[4]
         entry = traffic(fdir, wdir, copy_mib)
