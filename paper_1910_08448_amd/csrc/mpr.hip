@@ -164,7 +164,7 @@ __global__ __launch_bounds__(256) void k_sample_energy(GridInfo* gi, const doubl
 template <class S>
 __global__ __launch_bounds__(256) void k_map_init(const GcDesc* gcs, const GridInfo* gi,
                                                   const double* z, const uint8_t* mask,
-                                                  void* st0, void* st1, double* acc,
+                                                  void* st0, void* st1,
                                                   uint32_t key0, uint32_t key1)
 {
     using St = Store<S>;
@@ -201,8 +201,91 @@ __global__ __launch_bounds__(256) void k_map_init(const GcDesc* gcs, const GridI
         }
         ((typename St::raw*)st0)[g.plane_off + e] = v;
         ((typename St::raw*)st1)[g.plane_off + e] = v;
-        acc[g.plane_off + e] = 0.0;
     }
+}
+
+// Rank tables of the compact accumulators (acc_rank): for each grid, row y, colour c and block b
+// of 64 plane columns, the bit mask of its prediction sites (mask value 0 inside the grid) and
+// the number of prediction sites before the block in the order (y, c, k).  Built in four steps:
+// masks and block counts; per (y, c) row an exclusive scan of its blocks' counts and the row's
+// total; per grid an exclusive scan of the row totals; the row bases added to the blocks.
+__global__ __launch_bounds__(256) void k_rank_count(const GcDesc* gcs, int n_chains, const uint8_t* mask,
+                                                    uint64_t* rk_mask, int32_t* rk_base)
+{
+    const GcDesc g = gcs[blockIdx.y * n_chains];
+    const int nb = g.pitch >> 6;
+    const int64_t n = 2ll * g.H * nb;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int rowc = (int)(i / nb), b = (int)(i - (int64_t)rowc * nb);
+        const int y = rowc >> 1, c = rowc & 1;
+        const uint8_t* mrow = mask + g.grid_site_off + (int64_t)y * g.W;
+        uint64_t m = 0;
+        for (int t = 0; t < 64; ++t) {
+            const int x = 2 * (64 * b + t) + ((y + c) & 1);
+            if (x < g.W && mrow[x] == 0) m |= 1ull << t;
+        }
+        rk_mask[g.rk_off + i] = m;
+        rk_base[g.rk_off + i] = __popcll(m);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rank_rows(const GcDesc* gcs, int n_chains, int32_t* rk_base,
+                                                   int32_t* row_tot, const int64_t* row_off)
+{
+    const GcDesc g = gcs[blockIdx.y * n_chains];
+    const int nb = g.pitch >> 6;
+    for (int rowc = blockIdx.x * blockDim.x + threadIdx.x; rowc < 2 * g.H; rowc += gridDim.x * blockDim.x) {
+        int32_t* p = rk_base + g.rk_off + (int64_t)rowc * nb;
+        int32_t run = 0;
+        for (int b = 0; b < nb; ++b) { const int32_t v = p[b]; p[b] = run; run += v; }
+        row_tot[row_off[blockIdx.y] + rowc] = run;
+    }
+}
+
+// one block per grid: exclusive scan of the grid's 2 H row totals, in tiles of 1024
+__global__ __launch_bounds__(256) void k_rank_rowscan(const GcDesc* gcs, int n_chains, int32_t* row_tot,
+                                                      const int64_t* row_off)
+{
+    const GcDesc g = gcs[blockIdx.x * n_chains];
+    int32_t* p = row_tot + row_off[blockIdx.x];
+    const int n = 2 * g.H, tid = threadIdx.x;
+    __shared__ int32_t sh[256];
+    int32_t carry = 0;
+    for (int base = 0; base < n; base += 1024) {
+        int32_t v[4], t = 0;
+        for (int j = 0; j < 4; ++j) {
+            const int i = base + 4 * tid + j;
+            v[j] = i < n ? p[i] : 0;
+            t += v[j];
+        }
+        sh[tid] = t;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const int32_t add = tid >= off ? sh[tid - off] : 0;
+            __syncthreads();
+            sh[tid] += add;
+            __syncthreads();
+        }
+        int32_t r = sh[tid] - t + carry;
+        const int32_t total = sh[255];
+        __syncthreads();
+        for (int j = 0; j < 4; ++j) {
+            const int i = base + 4 * tid + j;
+            if (i < n) p[i] = r;
+            r += v[j];
+        }
+        carry += total;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rank_add(const GcDesc* gcs, int n_chains, int32_t* rk_base,
+                                                  const int32_t* row_tot, const int64_t* row_off)
+{
+    const GcDesc g = gcs[blockIdx.y * n_chains];
+    const int nb = g.pitch >> 6;
+    const int64_t n = 2ll * g.H * nb;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        rk_base[g.rk_off + i] += row_tot[row_off[blockIdx.y] + (int)(i / nb)];
 }
 
 __global__ __launch_bounds__(256) void k_copy_z(const GridInfo* gi, const double* z, double* zcopy)
@@ -377,6 +460,7 @@ __global__ __launch_bounds__(1024) void k_control(const GcDesc* gcs, GcCtl* ctl,
 template <class S>
 __global__ __launch_bounds__(256) void k_finalize(const GcDesc* gcs, const GridInfo* gi,
                                                   const void* st, const double* acc,
+                                                  const uint64_t* rk_mask, const int32_t* rk_base,
                                                   const double* zcopy, double* zhat,
                                                   int n_chains, int64_t n_avg)
 {
@@ -396,8 +480,9 @@ __global__ __launch_bounds__(256) void k_finalize(const GcDesc* gcs, const GridI
         if (St::sample(v)) out = zcopy[G.site_off + i];
         else {
             double m = 0.0;
+            const int64_t rank = acc_rank(rk_mask, rk_base, g0.rk_off, g0.pitch, c, (int)y, (int)(x >> 1));
             for (int ch = 0; ch < n_chains; ++ch)
-                m += acc[gcs[grid * n_chains + ch].plane_off + e] / (double)n_avg;
+                m += acc[gcs[grid * n_chains + ch].site_off + rank] / (double)n_avg;
             m /= (double)n_chains;
             out = G.zmin + (G.zmax - G.zmin) * m;
         }
@@ -407,7 +492,8 @@ __global__ __launch_bounds__(256) void k_finalize(const GcDesc* gcs, const GridI
 
 template <class S>
 __global__ __launch_bounds__(256) void k_get_state(const GcDesc* gcs, const void* st,
-                                                   const double* acc, double* u_out,
+                                                   const double* acc, const uint64_t* rk_mask,
+                                                   const int32_t* rk_base, double* u_out,
                                                    double* acc_out)
 {
     using St = Store<S>;
@@ -418,14 +504,18 @@ __global__ __launch_bounds__(256) void k_get_state(const GcDesc* gcs, const void
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t y = i / g.W, x = i - y * g.W;
         const int64_t e = g.plane_off + ((x + y) & 1) * per_plane + y * g.pitch + (x >> 1);
-        if (u_out) u_out[g.site_off + i] = St::template value<double>(((const typename St::raw*)st)[e]);
-        if (acc_out) acc_out[g.site_off + i] = acc[e];
+        const typename St::raw v = ((const typename St::raw*)st)[e];
+        if (u_out) u_out[g.site_off + i] = St::template value<double>(v);
+        if (acc_out)
+            acc_out[g.site_off + i] = St::sample(v) ? 0.0
+                : acc[g.site_off + acc_rank(rk_mask, rk_base, g.rk_off, g.pitch, (int)((x + y) & 1), (int)y, (int)(x >> 1))];
     }
 }
 
 // check (mode 0) or write (mode 1) prediction-site angles; flag 1 = value outside [0, 1]
 template <class S>
 __global__ __launch_bounds__(256) void k_set_state(const GcDesc* gcs, void* st, double* acc,
+                                                   const uint64_t* rk_mask, const int32_t* rk_base,
                                                    const double* u_in, const double* acc_in,
                                                    int* flag, int mode)
 {
@@ -447,7 +537,9 @@ __global__ __launch_bounds__(256) void k_set_state(const GcDesc* gcs, void* st, 
                 *p = St::template encode<double>(u);
             }
         }
-        if (acc_in && mode == 1) acc[e] = acc_in[g.site_off + i];
+        if (acc_in && mode == 1)
+            acc[g.site_off + acc_rank(rk_mask, rk_base, g.rk_off, g.pitch, (int)((x + y) & 1), (int)y, (int)(x >> 1))] =
+                acc_in[g.site_off + i];
     }
 }
 
@@ -735,7 +827,12 @@ struct mpr_ctx {
     RunCtl* d_dbg_run = nullptr;
     GridInfo* d_gi = nullptr;
     void* d_state[2] = {nullptr, nullptr};
-    double* d_acc = nullptr;
+    double* d_acc = nullptr;     // compact FP64 accumulators: [gc][rank], gc's at its site_off
+    uint64_t* d_rk_mask = nullptr;   // rank tables of the accumulators (acc_rank)
+    int32_t* d_rk_base = nullptr;
+    int32_t* d_rk_rows = nullptr;    // per grid and (y, c) row: totals, then their scan
+    int64_t* d_rk_row_off = nullptr; // per grid: its first row in d_rk_rows
+    int64_t rk_entries = 0, rk_rows = 0, chain_sites = 0;
     double* d_zcopy = nullptr;
     int64_t* d_e_part = nullptr;
     int32_t* d_a_part = nullptr;
@@ -839,13 +936,15 @@ static void free_device(mpr_ctx* c)
     c->graphs.clear();
     void* ptrs[] = {c->d_gcs, c->d_items, c->d_ctl, c->d_run, c->d_dbg_run, c->d_gi,
                     c->d_state[0], c->d_state[1], c->d_acc, c->d_zcopy, c->d_e_part,
-                    c->d_a_part, c->d_trace, c->d_flag, c->d_ictl, c->d_gacc};
+                    c->d_a_part, c->d_trace, c->d_flag, c->d_ictl, c->d_gacc,
+                    c->d_rk_mask, c->d_rk_base, c->d_rk_rows, c->d_rk_row_off};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     c->d_gcs = nullptr; c->d_items = nullptr; c->d_ctl = nullptr; c->d_run = nullptr;
     c->d_dbg_run = nullptr; c->d_gi = nullptr; c->d_state[0] = c->d_state[1] = nullptr;
     c->d_acc = nullptr; c->d_zcopy = nullptr; c->d_e_part = nullptr; c->d_a_part = nullptr;
     c->d_trace = nullptr; c->d_flag = nullptr; c->d_ictl = nullptr; c->d_gacc = nullptr;
+    c->d_rk_mask = nullptr; c->d_rk_base = nullptr; c->d_rk_rows = nullptr; c->d_rk_row_off = nullptr;
     c->trace_cap = 0;
     void* lists[] = {c->d_sites, c->d_waves[0], c->d_waves[1], c->d_lead[0], c->d_lead[1],
                      c->d_econst, c->d_rowcnt, c->d_tiles};
@@ -955,8 +1054,12 @@ static int setup_shapes(mpr_ctx* c, int G, const int64_t* H, const int64_t* W)
     for (int g = 0; g < G; ++g) { c->site_off[g] = off; off += H[g] * W[g]; }
     c->n_grid_sites = off;
     c->gcs.clear();
-    int64_t plane = 0;
-    for (int g = 0; g < G; ++g)
+    int64_t plane = 0, rk = 0, rk_rows = 0;
+    for (int g = 0; g < G; ++g) {
+        const int64_t np_g = ((W[g] + 1) / 2 + 1) / 2, pitch_g = ((2 * np_g + 63) / 64) * 64;
+        const int64_t rk_g = rk;
+        rk += 2 * H[g] * (pitch_g / 64);
+        rk_rows += 2 * H[g];
         for (int ch = 0; ch < c->C; ++ch) {
             GcDesc d{};
             d.H = (int32_t)H[g];
@@ -971,8 +1074,12 @@ static int setup_shapes(mpr_ctx* c, int G, const int64_t* H, const int64_t* W)
             d.grid_site_off = c->site_off[g];
             d.n_bonds = per ? 2 * H[g] * W[g] : 2 * H[g] * W[g] - H[g] - W[g];
             d.inv_n_bonds = d.n_bonds > 0 ? 1.0 / (double)d.n_bonds : 0.0;
+            d.rk_off = rk_g;
             c->gcs.push_back(d);
         }
+    }
+    c->rk_entries = rk;
+    c->rk_rows = rk_rows;
     c->rows = choose_rows(c);
     build_items(c, c->rows);
     const int rmin = std::min(c->rows, 2);
@@ -983,6 +1090,7 @@ static int setup_shapes(mpr_ctx* c, int G, const int64_t* H, const int64_t* W)
     int64_t so = 0;
     for (int g = 0; g < G; ++g)
         for (int ch = 0; ch < c->C; ++ch) { c->gcs[g * c->C + ch].site_off = so; so += H[g] * W[g]; }
+    c->chain_sites = so;
     c->plane_elems = plane;
     return MPR_OK;
 }
@@ -1021,7 +1129,17 @@ static int alloc_device(mpr_ctx* c)
     HIPCHK(c, hipMalloc(&c->d_dbg_run, sizeof(RunCtl)));
     HIPCHK(c, hipMalloc(&c->d_gi, c->G * sizeof(GridInfo)));
     for (int b = 0; b < 2; ++b) HIPCHK(c, hipMalloc(&c->d_state[b], c->plane_elems * c->elem));
-    HIPCHK(c, hipMalloc(&c->d_acc, c->plane_elems * sizeof(double)));
+    HIPCHK(c, hipMalloc(&c->d_acc, c->chain_sites * sizeof(double)));
+    HIPCHK(c, hipMalloc(&c->d_rk_mask, std::max<int64_t>(c->rk_entries, 1) * sizeof(uint64_t)));
+    HIPCHK(c, hipMalloc(&c->d_rk_base, std::max<int64_t>(c->rk_entries, 1) * sizeof(int32_t)));
+    HIPCHK(c, hipMalloc(&c->d_rk_rows, std::max<int64_t>(c->rk_rows, 1) * sizeof(int32_t)));
+    HIPCHK(c, hipMalloc(&c->d_rk_row_off, c->G * sizeof(int64_t)));
+    {
+        std::vector<int64_t> ro(c->G);
+        int64_t r = 0;
+        for (int g = 0; g < c->G; ++g) { ro[g] = r; r += 2 * c->H[g]; }
+        HIPCHK(c, h2d(c, c->d_rk_row_off, ro.data(), c->G * sizeof(int64_t)));
+    }
     HIPCHK(c, hipMalloc(&c->d_zcopy, c->n_grid_sites * sizeof(double)));
     HIPCHK(c, hipMalloc(&c->d_e_part, 2 * c->item_cap * sizeof(int64_t)));
     HIPCHK(c, hipMalloc(&c->d_a_part, c->item_cap * sizeof(int32_t)));
@@ -1047,17 +1165,17 @@ template <class S> static void launch_map(mpr_ctx* c, const double* z, const uin
     for (auto& g : c->gcs) maxp = std::max<int64_t>(maxp, 2 * (int64_t)g.H * g.pitch);
     const uint32_t k0 = (uint32_t)(c->cfg.seed & 0xffffffffu), k1 = (uint32_t)(c->cfg.seed >> 32);
     hipLaunchKernelGGL(k_map_init<S>, site_grid(maxp, (int)c->gcs.size()), dim3(256), 0, c->stream,
-                       c->d_gcs, c->d_gi, z, mask, c->d_state[0], c->d_state[1], c->d_acc,
+                       c->d_gcs, c->d_gi, z, mask, c->d_state[0], c->d_state[1],
                        k0, k1);
 }
 
 template <class S> static void launch_get_state(mpr_ctx* c, double* u, double* acc, dim3 grid)
 {
-    hipLaunchKernelGGL(k_get_state<S>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_state[c->cur], c->d_acc, u, acc);
+    hipLaunchKernelGGL(k_get_state<S>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_state[c->cur], c->d_acc, c->d_rk_mask, c->d_rk_base, u, acc);
 }
 template <class S> static void launch_set_state(mpr_ctx* c, const double* u, const double* acc, int mode, dim3 grid)
 {
-    hipLaunchKernelGGL(k_set_state<S>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_state[c->cur], c->d_acc, u, acc, c->d_flag, mode);
+    hipLaunchKernelGGL(k_set_state<S>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_state[c->cur], c->d_acc, c->d_rk_mask, c->d_rk_base, u, acc, c->d_flag, mode);
 }
 
 // grow a device buffer to at least `bytes` (contents dropped); captured graphs hold the old
@@ -1449,6 +1567,25 @@ static int load_common(mpr_ctx* c, const double* z, const uint8_t* mask, bool fr
     default: launch_map<_Float16>(c, z, mask); break;
     }
     HIPCHK(c, hipGetLastError());
+    // compact accumulators: zeroed, and the rank tables of this data's prediction sites
+    HIPCHK(c, hipMemsetAsync(c->d_acc, 0, c->chain_sites * sizeof(double), c->stream));
+    {
+        int64_t max_e = 0, max_rows = 0;
+        for (int g = 0; g < c->G; ++g) {
+            const GcDesc& d = c->gcs[(size_t)g * c->C];
+            max_e = std::max<int64_t>(max_e, 2 * (int64_t)d.H * (d.pitch / 64));
+            max_rows = std::max<int64_t>(max_rows, 2 * (int64_t)d.H);
+        }
+        hipLaunchKernelGGL(k_rank_count, site_grid(max_e, c->G, 1024), dim3(256), 0, c->stream, c->d_gcs, c->C,
+                           mask, c->d_rk_mask, c->d_rk_base);
+        hipLaunchKernelGGL(k_rank_rows, site_grid(max_rows, c->G, 64), dim3(256), 0, c->stream, c->d_gcs, c->C,
+                           c->d_rk_base, c->d_rk_rows, c->d_rk_row_off);
+        hipLaunchKernelGGL(k_rank_rowscan, dim3((unsigned)c->G), dim3(256), 0, c->stream, c->d_gcs, c->C,
+                           c->d_rk_rows, c->d_rk_row_off);
+        hipLaunchKernelGGL(k_rank_add, site_grid(max_e, c->G, 1024), dim3(256), 0, c->stream, c->d_gcs, c->C,
+                           c->d_rk_base, c->d_rk_rows, c->d_rk_row_off);
+        HIPCHK(c, hipGetLastError());
+    }
     HIPCHK(c, hipMemcpyAsync(c->gi.data(), c->d_gi, c->G * sizeof(GridInfo), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     std::vector<GcCtl> ctl(c->gcs.size());
@@ -1548,6 +1685,8 @@ static void enqueue_tiled(mpr_ctx* c, int flags, int sweep_off, int src_buf, con
     a.src = c->d_state[src_buf];
     a.dst = c->d_state[1 - src_buf];
     a.acc = c->d_acc;
+    a.rk_mask = c->d_rk_mask;
+    a.rk_base = c->d_rk_base;
     a.dec = dec;
     a.ictl = c->d_ictl;
     a.gacc = c->d_gacc;
@@ -1598,6 +1737,8 @@ static void enqueue_sparse(mpr_ctx* c, int flags, int sweep_off, const RunCtl* r
         a.run = run;
         a.state = c->d_state[c->cur];
         a.acc = c->d_acc;
+        a.rk_mask = c->d_rk_mask;
+        a.rk_base = c->d_rk_base;
         a.dec = dec;
         a.ictl = c->d_ictl;
         a.gacc = c->d_gacc;
@@ -1643,6 +1784,8 @@ static void enqueue_sweep(mpr_ctx* c, int flags, int sweep_off, int src_buf, con
     a.src = c->d_state[src_buf];
     a.dst = c->d_state[1 - src_buf];
     a.acc = c->d_acc;
+    a.rk_mask = c->d_rk_mask;
+    a.rk_base = c->d_rk_base;
     a.dec = dec;
     a.e_part = c->d_e_part;
     a.a_part = c->d_a_part;
@@ -1980,10 +2123,10 @@ int mpr_get_predictions(mpr_ctx* c, double* zhat)
     rc = mark(c, PHASE_PREDICT, 0);
     if (rc) return rc;
     switch (c->sprec) {
-    case MPR_FP64: hipLaunchKernelGGL(k_finalize<double>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_gi, c->d_state[c->cur], c->d_acc, c->d_zcopy, zhat, c->C, c->n_avg); break;
-    case MPR_FP32: hipLaunchKernelGGL(k_finalize<float>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_gi, c->d_state[c->cur], c->d_acc, c->d_zcopy, zhat, c->C, c->n_avg); break;
-    case MPR_FIX16: hipLaunchKernelGGL(k_finalize<Fix15>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_gi, c->d_state[c->cur], c->d_acc, c->d_zcopy, zhat, c->C, c->n_avg); break;
-    default: hipLaunchKernelGGL(k_finalize<_Float16>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_gi, c->d_state[c->cur], c->d_acc, c->d_zcopy, zhat, c->C, c->n_avg); break;
+    case MPR_FP64: hipLaunchKernelGGL(k_finalize<double>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_gi, c->d_state[c->cur], c->d_acc, c->d_rk_mask, c->d_rk_base, c->d_zcopy, zhat, c->C, c->n_avg); break;
+    case MPR_FP32: hipLaunchKernelGGL(k_finalize<float>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_gi, c->d_state[c->cur], c->d_acc, c->d_rk_mask, c->d_rk_base, c->d_zcopy, zhat, c->C, c->n_avg); break;
+    case MPR_FIX16: hipLaunchKernelGGL(k_finalize<Fix15>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_gi, c->d_state[c->cur], c->d_acc, c->d_rk_mask, c->d_rk_base, c->d_zcopy, zhat, c->C, c->n_avg); break;
+    default: hipLaunchKernelGGL(k_finalize<_Float16>, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_gi, c->d_state[c->cur], c->d_acc, c->d_rk_mask, c->d_rk_base, c->d_zcopy, zhat, c->C, c->n_avg); break;
     }
     HIPCHK(c, hipGetLastError());
     return mark(c, PHASE_PREDICT, 1);
@@ -2225,6 +2368,17 @@ static int use_rows(mpr_ctx* c, int rows)
     return MPR_OK;
 }
 
+// the tile shape the automatic rule gives this context (see build_tiles_t)
+static int rule_shape(const mpr_ctx* c)
+{
+    if (!c->fsingle) return kShapeW4Base;
+    const int base_rows = (c->sprec == MPR_FP64) ? 8 : 16;   // tile_rows<S, float>()
+    int64_t base = 0;
+    for (const GcDesc& d : c->gcs)
+        base += (int64_t)((d.H + base_rows - 1) / base_rows) * ((d.wc + kTileCols - 1) / kTileCols);
+    return base < kTileWavesSwitch ? kShapeW8Tall : kShapeW4Base;
+}
+
 static const int kGraphCandidates[] = {16, 32, 64};
 static bool tune_graphs(const mpr_ctx* c) { return c->cfg.graph_sweeps == 0 && c->stream != nullptr; }
 
@@ -2397,6 +2551,23 @@ static int autotune(mpr_ctx* c, int n, int* best_out)
             best = cands[k];
             if (best.path == MPR_SWEEP_TILED && !pick_shape) best.shape = -1;
         }
+    // the rule's own configuration stays unless a candidate beats it by more than 3 % (timings
+    // of candidates a few per cent apart vary between runs)
+    {
+        const int rule_path = pick_path ? auto_path(c) : current_path(c);
+        const int rule_rows = choose_rows(c);
+        for (size_t k = 0; k < cands.size(); ++k) {
+            const TuneChoice& t = cands[k];
+            const bool is_rule = t.path == rule_path &&
+                                 (t.path != MPR_SWEEP_FUSED || t.rows == rule_rows) &&
+                                 (t.path != MPR_SWEEP_TILED || t.shape == rule_shape(c));
+            if (is_rule && best_t[k] <= 1.03f * best_ms) {
+                best = t;
+                if (best.path == MPR_SWEEP_TILED) best.shape = -1;
+                break;
+            }
+        }
+    }
     // sweeps per graph, on the winning path
     if (!rc && tune_graphs(c)) {
         rc = finish(best);
@@ -2410,6 +2581,7 @@ static int autotune(mpr_ctx* c, int n, int* best_out)
         float bg = 1e30f;
         for (int i = 0; i < 3; ++i)
             if (best_g[i] < bg) { bg = best_g[i]; best.graph_k = kGraphCandidates[i]; }
+        if (best_g[1] <= 1.03f * bg) best.graph_k = kGraphCandidates[1];   // the default, 32, unless clearly slower
     }
     (void)hipStreamSynchronize(c->stream);
     (void)hipEventDestroy(e0);

@@ -33,6 +33,7 @@ struct GcDesc {            // one (grid, chain)
     int64_t n_bonds;       // nearest-neighbour bonds of the grid
     double inv_n_pred;     // 1 / n_pred (0 without prediction sites), 1 / n_bonds: the control
     double inv_n_bonds;    // step multiplies instead of dividing (every wave evaluates it)
+    int64_t rk_off;        // first entry of the grid's rank tables (see acc_rank)
 };
 
 struct Item {              // one wave's work: 60 output pairs x rows [y0, y1)
@@ -92,6 +93,8 @@ struct SweepArgs {
     const void* src;
     void* dst;
     double* acc;
+    const uint64_t* rk_mask;   // rank tables of the compact accumulators (see acc_rank)
+    const int32_t* rk_base;
     uint8_t* dec;
     int64_t* e_part;           // per item: energy partial [2] (two-word fixed point, or float bits)
     int32_t* a_part;           // per item: accepted moves
@@ -344,6 +347,20 @@ __device__ __forceinline__ double2 buf_load_f64x2(Rsrc r, uint32_t off)
                         __longlong_as_double((long long)(((uint64_t)v.w << 32) | v.z)));
 }
 
+__device__ __forceinline__ double buf_load_f64(Rsrc r, uint32_t off)
+{
+    const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+    return __longlong_as_double((long long)(((uint64_t)v.y << 32) | v.x));
+}
+
+__device__ __forceinline__ void buf_store_f64(Rsrc r, uint32_t off, double d)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(d);
+    u32x2_t v;
+    v.x = (uint32_t)b; v.y = (uint32_t)(b >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, 0);
+}
+
 __device__ __forceinline__ void buf_store_f64x2(Rsrc r, uint32_t off, double2 d)
 {
     const uint64_t a = (uint64_t)__double_as_longlong(d.x), b = (uint64_t)__double_as_longlong(d.y);
@@ -427,6 +444,21 @@ __host__ __device__ inline double fix2_value(int64_t hi, int64_t lo)
     const double k32 = 4294967296.0;
     const int64_t hi_top = hi >> 20, hi_bot = hi - (hi_top << 20);
     return (double)hi_top * 1048576.0 / k32 + ((double)hi_bot / k32 + (double)lo / (k32 * k32));
+}
+
+// Compact accumulators.  The FP64 running sums of the averaging sweeps are kept for prediction
+// sites only: (grid, chain) gc's sums occupy acc[site_off + rank], rank = the site's position
+// among its grid's prediction sites in the order (row y, colour c, plane column k).  Two tables
+// per grid give the rank of any plane element: for each (y, c) row and each block of 64 plane
+// columns, a bit mask of its prediction sites and the number of prediction sites before the block
+// (tables entry rk_off + (2 y + c) nb + block, nb = pitch / 64).  The averaging sweeps then read
+// and write 16 bytes per prediction site instead of per site.
+__device__ __forceinline__ int64_t acc_rank(const uint64_t* rk_mask, const int32_t* rk_base,
+                                            int64_t rk_off, int pitch, int c, int y, int k)
+{
+    const int64_t i = rk_off + (int64_t)(2 * y + c) * (pitch >> 6) + (k >> 6);
+    const uint64_t below = (1ull << (k & 63)) - 1ull;
+    return (int64_t)rk_base[i] + (int64_t)__popcll(rk_mask[i] & below);
 }
 
 // One step of the temperature and window control after an inference sweep (the multiplicative
@@ -751,20 +783,28 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
             else { const Fix2 f = fixed64x2((double)eo); e_hi += f.hi; e_lo += f.lo; }
         }
         if (FLAGS & F_ACC) {
-            const Rsrc ra = make_rsrc(a.acc + it.plane_off, gc_elems * 8u);
-            const uint32_t o0 = out_lane ? r0 * 8u : kBufOOB, o1 = out_lane ? r1 * 8u : kBufOOB;
-            const bool f0a = exists(y, par, 0) & !St::sample(n0.a);
-            const bool f0b = exists(y, par, 1) & !St::sample(n0.b);
-            const bool f1a = exists(y, par ^ 1, 0) & !St::sample(n1.a);
-            const bool f1b = exists(y, par ^ 1, 1) & !St::sample(n1.b);
-            double2 p0 = buf_load_f64x2(ra, o0);
-            double2 p1 = buf_load_f64x2(ra, o1);
-            if (f0a) p0.x += St::template value<double>(n0.a);
-            if (f0b) p0.y += St::template value<double>(n0.b);
-            if (f1a) p1.x += St::template value<double>(n1.a);
-            if (f1b) p1.y += St::template value<double>(n1.b);
-            buf_store_f64x2(ra, o0, p0);
-            buf_store_f64x2(ra, o1, p1);
+            // compact accumulators: the ranks of this lane's prediction sites (member 1 follows
+            // member 0 when both are prediction sites: 2 jj is even, so both share a mask block)
+            const Rsrc ra = make_rsrc(a.acc + g.site_off, (uint32_t)(it.H * it.W) * 8u);
+            const bool f0a = out_lane & exists(y, par, 0) & !St::sample(n0.a);
+            const bool f0b = out_lane & exists(y, par, 1) & !St::sample(n0.b);
+            const bool f1a = out_lane & exists(y, par ^ 1, 0) & !St::sample(n1.a);
+            const bool f1b = out_lane & exists(y, par ^ 1, 1) & !St::sample(n1.b);
+            const int ck = out_lane ? col : 0;          // halo lanes' columns may lie outside the grid
+            const int64_t k0 = acc_rank(a.rk_mask, a.rk_base, g.rk_off, pitch, 0, y, ck);
+            const int64_t k1 = acc_rank(a.rk_mask, a.rk_base, g.rk_off, pitch, 1, y, ck);
+            const uint32_t o0a = f0a ? (uint32_t)k0 * 8u : kBufOOB, o0b = f0b ? (uint32_t)(k0 + f0a) * 8u : kBufOOB;
+            const uint32_t o1a = f1a ? (uint32_t)k1 * 8u : kBufOOB, o1b = f1b ? (uint32_t)(k1 + f1a) * 8u : kBufOOB;
+            double s0a = buf_load_f64(ra, o0a), s0b = buf_load_f64(ra, o0b);
+            double s1a = buf_load_f64(ra, o1a), s1b = buf_load_f64(ra, o1b);
+            s0a += St::template value<double>(n0.a);
+            s0b += St::template value<double>(n0.b);
+            s1a += St::template value<double>(n1.a);
+            s1b += St::template value<double>(n1.b);
+            buf_store_f64(ra, o0a, s0a);
+            buf_store_f64(ra, o0b, s0b);
+            buf_store_f64(ra, o1a, s1a);
+            buf_store_f64(ra, o1b, s1b);
         }
         if ((FLAGS & F_DEC) && out_lane) {
             uint8_t* d = a.dec + g.site_off + (int64_t)y * g.W;
@@ -843,10 +883,12 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
             buf_store_pair<St>(rd, kBufOOB, Pair{0, 0});
             buf_store_pair<St>(rd, kBufOOB, Pair{0, 0});
             if (FLAGS & F_ACC) {
-                const Rsrc ra = make_rsrc(a.acc + it.plane_off, gc_elems * 8u);
-                const double2 p0 = buf_load_f64x2(ra, kBufOOB), p1 = buf_load_f64x2(ra, kBufOOB);
-                buf_store_f64x2(ra, kBufOOB, p0);
-                buf_store_f64x2(ra, kBufOOB, p1);
+                const Rsrc ra = make_rsrc(a.acc + g.site_off, (uint32_t)(it.H * it.W) * 8u);
+                double s[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) s[m] = buf_load_f64(ra, kBufOOB);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) buf_store_f64(ra, kBufOOB, s[m]);
             }
         }
     };

@@ -27,6 +27,8 @@ struct SparseArgs {
     const RunCtl* run;
     void* state;               // state planes, updated in place
     double* acc;
+    const uint64_t* rk_mask;   // rank tables of the compact accumulators (see acc_rank)
+    const int32_t* rk_base;
     uint8_t* dec;
     GcCtl* ictl;
     int64_t* gacc;
@@ -173,15 +175,9 @@ __global__ __launch_bounds__(256) void k_sparse(SparseArgs a)
         e_lo = f.lo;
     }
     if (FLAGS & F_ACC) {
-        const Rsrc ra = make_rsrc(a.acc + g.plane_off, 2u * (uint32_t)plane_sz * 8u);
-        const uint32_t ao = is_free ? own * 8u : kBufOOB;
-        const u32x2_t p = __builtin_amdgcn_raw_buffer_load_b64(ra, (int)ao, 0, 0);
-        double d = __longlong_as_double((long long)(((uint64_t)p.y << 32) | p.x));
-        d += St::template value<double>(nv);
-        const uint64_t b = (uint64_t)__double_as_longlong(d);
-        u32x2_t w;
-        w.x = (uint32_t)b; w.y = (uint32_t)(b >> 32);
-        __builtin_amdgcn_raw_buffer_store_b64(w, ra, (int)ao, 0, 0);
+        const Rsrc ra = make_rsrc(a.acc + g.site_off, (uint32_t)(H * W) * 8u);
+        const uint32_t ao = is_free ? (uint32_t)acc_rank(a.rk_mask, a.rk_base, g.rk_off, pitch, C, y, k) * 8u : kBufOOB;
+        buf_store_f64(ra, ao, buf_load_f64(ra, ao) + St::template value<double>(nv));
     }
     if ((FLAGS & F_DEC) && is_free) a.dec[g.site_off + (int64_t)y * W + x] = (uint8_t)o.dec;
 

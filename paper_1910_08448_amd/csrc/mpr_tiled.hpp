@@ -60,6 +60,8 @@ struct TiledArgs {
     const void* src;
     void* dst;
     double* acc;
+    const uint64_t* rk_mask;   // rank tables of the compact accumulators (see acc_rank)
+    const int32_t* rk_base;
     uint8_t* dec;
     GcCtl* ictl;
     int64_t* gacc;
@@ -292,15 +294,10 @@ __global__ __launch_bounds__(NW * kWave) void k_tiled(TiledArgs a)
 
     int n_acc = 0;
     int64_t e_hi = 0, e_lo = 0;
-    const Rsrc ra = make_rsrc(a.acc + g.plane_off, 2u * (uint32_t)plane_sz * 8u);
-    auto accumulate = [&](uint32_t elem, Raw nv) {
-        const u32x2_t p = __builtin_amdgcn_raw_buffer_load_b64(ra, (int)(elem * 8u), 0, 0);
-        double d = __longlong_as_double((long long)(((uint64_t)p.y << 32) | p.x));
-        d += St::template value<double>(nv);
-        const uint64_t b = (uint64_t)__double_as_longlong(d);
-        u32x2_t w;
-        w.x = (uint32_t)b; w.y = (uint32_t)(b >> 32);
-        __builtin_amdgcn_raw_buffer_store_b64(w, ra, (int)(elem * 8u), 0, 0);
+    const Rsrc ra = make_rsrc(a.acc + g.site_off, (uint32_t)(H * W) * 8u);
+    auto accumulate = [&](int c, int yy, int kk, Raw nv) {
+        const uint32_t ao = (uint32_t)acc_rank(a.rk_mask, a.rk_base, g.rk_off, pitch, c, yy, kk) * 8u;
+        buf_store_f64(ra, ao, buf_load_f64(ra, ao) + St::template value<double>(nv));
     };
 
     // colour 0: the tile and its ring, from the old colour-1 stage
@@ -340,7 +337,7 @@ __global__ __launch_bounds__(NW * kWave) void k_tiled(TiledArgs a)
                 e_hi += f.hi;
                 e_lo += f.lo;
             }
-            if (FLAGS & F_ACC) accumulate(elem, nv);
+            if (FLAGS & F_ACC) accumulate(0, yy, kk, nv);
             if (FLAGS & F_DEC) a.dec[g.site_off + (int64_t)yy * W + 2 * kk + p] = (uint8_t)o.dec;
         }
     }
@@ -371,7 +368,7 @@ __global__ __launch_bounds__(NW * kWave) void k_tiled(TiledArgs a)
             e_hi += f.hi;
             e_lo += f.lo;
         }
-        if (FLAGS & F_ACC) accumulate(elem, nv);
+        if (FLAGS & F_ACC) accumulate(1, yy, kk, nv);
         if (FLAGS & F_DEC) a.dec[g.site_off + (int64_t)yy * W + 2 * kk + p] = (uint8_t)o.dec;
     }
 
