@@ -432,7 +432,7 @@ def main():
                    "sweep_path": prim["sweep_path"], "tuning": prim["tuning"]},
         "fp64_factor": (prim["value"] / fp64["value"]) if fp64 else None,
         "mae": prim["mae"], "rmse": prim["rmse"], "T_hat": prim["T_hat"],
-        "T_hat_clamped": prim["T_hat_clamped"],
+        "T_hat_clamped": prim["T_hat_clamped"], "phase_ms_last_step": prim["phase_ms_last_step"],
         "roofline": prim["roofline"],
         "cpu_baseline": cpu,
         "setups": setups,
