@@ -958,13 +958,26 @@ static void free_device(mpr_ctx* c)
     c->alloc_sig.clear();
 }
 
-// work items: per (grid, chain), row blocks of `rows` rows x strips of 60 lane pairs
+// Work items: per (grid, chain), row blocks of `rows` rows x strips of 60 lane pairs.  When the
+// last strip holds at most 28 pairs (half a wave's output lanes) and `rows` is even, the last
+// strips of row blocks b and b + 1 share one two-half item (dy = rows) if every row the two
+// blocks read, y0(b) - 2 ... y1(b + 1) + 1, lies inside the grid: row blocks 1, 2 | 3, 4 | ...
+// up to the last block that ends at least two rows above the bottom.
+static int64_t two_half_items(int64_t np, int64_t H, int rows)
+{
+    const int64_t last = np - kOutPairs * ((np - 1) / kOutPairs);
+    if (rows % 2 || last > kHalfOutPairs) return 0;
+    const int64_t inner = (H - 2) / rows - 1;          // blocks 1 ... (H - 2) / rows - 1 qualify
+    return inner > 0 ? inner / 2 : 0;
+}
+
 static int64_t count_items(const mpr_ctx* c, int rows)
 {
     int64_t n = 0;
     for (int g = 0; g < c->G; ++g) {
         const int64_t np = ((c->W[g] + 1) / 2 + 1) / 2;
-        n += c->C * ((np + kOutPairs - 1) / kOutPairs) * ((c->H[g] + rows - 1) / rows);
+        const int64_t per = ((np + kOutPairs - 1) / kOutPairs) * ((c->H[g] + rows - 1) / rows);
+        n += c->C * (per - two_half_items(np, c->H[g], rows));
     }
     return n;
 }
@@ -1005,7 +1018,8 @@ static int choose_rows(const mpr_ctx* c)
     return best;
 }
 
-// work items of every (grid, chain): row blocks of `rows` rows x strips of 60 lane pairs
+// work items of every (grid, chain): row blocks of `rows` rows x strips of 60 lane pairs, the
+// last strips of pairs of full row blocks in two-half items where they fit (count_items)
 static void build_items(mpr_ctx* c, int rows)
 {
     c->items.clear();
@@ -1013,10 +1027,15 @@ static void build_items(mpr_ctx* c, int rows)
     for (size_t i = 0; i < c->gcs.size(); ++i) {
         GcDesc& d = c->gcs[i];
         d.item_begin = (int32_t)c->items.size();
-        for (int y0 = 0; y0 < d.H; y0 += rows)
-            for (int p0 = 0; p0 < d.np; p0 += kOutPairs)
+        const int64_t n_two = two_half_items(d.np, d.H, rows);   // blocks 1 ... 2 n_two
+        const int last_p0 = kOutPairs * ((d.np - 1) / kOutPairs);
+        for (int y0 = 0, b = 0; y0 < d.H; y0 += rows, ++b)
+            for (int p0 = 0; p0 < d.np; p0 += kOutPairs) {
+                const bool two = p0 == last_p0 && b >= 1 && b <= 2 * n_two;
+                if (two && !(b & 1)) continue;                  // swept by block b - 1's item
                 c->items.push_back(Item{(int32_t)i, p0, y0, std::min(d.H, y0 + rows), d.plane_off,
-                                        d.H, d.W, d.np, d.pitch});
+                                        d.H, d.W, d.np, d.pitch, two ? rows : 0, 0});
+            }
         d.item_end = (int32_t)c->items.size();
         max_items = std::max(max_items, d.item_end - d.item_begin);
     }

@@ -42,6 +42,10 @@ struct Item {              // one wave's work: 60 output pairs x rows [y0, y1)
     // single table read
     int64_t plane_off;
     int32_t H, W, np, pitch;
+    // dy > 0: two half-wave items of at most kHalfOutPairs output pairs each, lanes 0-31 on rows
+    // [y0, y1) and lanes 32-63 on rows [y0 + dy, y1 + dy) of the same columns (dy even); both
+    // halves' rows with their halos, y0 - 2 ... y1 + dy + 1, lie inside the grid
+    int32_t dy, pad;
 };
 
 struct GcCtl {             // per (grid, chain) control state, device resident
@@ -83,6 +87,7 @@ enum { DEC_OR = 1, DEC_ACCEPT = 2, DEC_OUTSIDE = 4 };
 constexpr int kWave = 64;
 constexpr int kPrefetchRows = 1;   // rows of both colours loaded ahead of use (2-4 measured no faster)
 constexpr int kOutPairs = 60;      // output pairs per wave (2 halo lanes on each side)
+constexpr int kHalfOutPairs = 28;  // output pairs per half wave of a two-half item
 constexpr int kWavesPerBlock = 4;
 
 struct SweepArgs {
@@ -634,13 +639,20 @@ template <class F> struct RowCS { F c0, s0, c1, s1; };
 
 // ------------------------------------------------------------------ fused sweep kernel
 // One wave = one work item: 64 lanes hold pairs pair0-2 .. pair0+61 of one (grid, chain);
-// lanes 2..61 are output lanes.  The wave walks down rows y0-2 .. y1+1 keeping a 3-row window:
+// lanes 2..61 are output lanes.  A two-half item (dy > 0) holds pairs pair0-2 .. pair0+29 in
+// each half, output lanes 2..29 of the half, the upper half dy rows further down: the ragged
+// last strips of two row blocks then fill one wave.  The wave walks the rows k of the lower
+// half; the upper half's row is k + dy, which enters only the lanes' address and counter
+// offsets: every row of a two-half item lies inside the grid, so the row tests (and the
+// periodic wrap) stay the same for both halves and wave-uniform.  The wave walks down rows y0-2 .. y1+1 keeping a 3-row window:
 // the old colour-1 (cos, sin) feed the colour-0 update of the middle row, the new colour-0
 // (cos, sin) of three rows feed the colour-1 update one row behind.  Halo lanes and rows
 // repeat their neighbours' colour-0 updates bit for bit (same inputs, same counters), so
 // items never exchange data within a sweep; the sweep reads `src` and writes `dst`.
+// Single-precision functions: at least five waves per SIMD (at most 96 VGPRs; the compiler's own
+// choice for some variants is four waves with up to 128).
 template <class S, class F, int FLAGS, bool ESINGLE, bool PER>
-__global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(F) == 4 ? 5 : 1))) void k_sweep(SweepArgs a)
 {
     using St = Store<S>;
     using M = Math<F>;
@@ -670,15 +682,22 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
     const F kexp = (sizeof(F) == 4) ? (F)(-1.4426950408889634 / ctl.T) : (F)(-1.0 / ctl.T);
 
     const int H = it.H, np = it.np, pitch = it.pitch;
-    const int j = it.pair0 - 2 + lane;
+    const bool halves = it.dy > 0;
+    const int hl = halves ? (lane & (kWave / 2 - 1)) : lane;      // lane within its half
+    const int yoff = (halves & (lane >= kWave / 2)) ? it.dy : 0;  // this lane's row = k + yoff
+    const int j = it.pair0 - 2 + hl;
     const bool in_range = (j >= 0) & (j < np);
     const int jj = PER ? ((j % np) + np) % np : j;        // periodic: W % 4 == 0, so wc is even
     const bool lane_ok = PER | in_range;
-    const bool out_lane = (lane >= 2) & (lane < kWave - 2) & in_range;
+    const bool out_lane = (hl >= 2) & (hl < (halves ? kWave / 2 - 2 : kWave - 2)) & in_range;
     // site (y, c, m) of this lane has x = 4 jj + 2 m + ((y + c) & 1); it exists iff x < W
     const int wl = it.W - 4 * jj;
     const int col = 2 * jj;                              // plane column of member 0
     const int plane_sz = H * pitch;                      // 16 plane_sz <= kBufMaxBytes (host check)
+    // lane offsets of row k: element (k + yoff) pitch + col of a plane, Philox counter word
+    // (k + yoff) np + jj
+    const int lane_elem = yoff * pitch + col;
+    const int lane_ctr = yoff * np + jj;
 
     // this (grid, chain)'s two planes in the source and destination buffers, and its accumulators
     // (offsets count stored elements: the tag type of a fixed-point storage has no size of its own)
@@ -693,12 +712,13 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
     // existence of member m at row parity p (= (y + c) & 1), rows aside: bit 2 m + p of ex_bits
     // (a value, not four addressable flags, so selecting one never goes through memory)
     const int ex_bits = lane_ok ? ((0 < wl) ? 1 : 0) | ((1 < wl) ? 2 : 0) | ((2 < wl) ? 4 : 0) | ((3 < wl) ? 8 : 0) : 0;
-    // (par = (y + c) & 1 is passed by the caller: in the unrolled steady state it is a constant)
+    // (par = (y + c) & 1 is passed by the caller: in the unrolled steady state it is a constant;
+    // dy is even, so it is the parity of the upper half's row too)
     auto exists = [=](int y, int par, int m) -> bool {
         return (((ex_bits >> (2 * m + par)) & 1) != 0) & row_ok(y);
     };
     auto load_pair = [&](int c, int y) -> Pair {
-        const uint32_t off = (lane_ok & row_ok(y)) ? (uint32_t)(c * plane_sz + wrap(y) * pitch + col) * kRaw : kBufOOB;
+        const uint32_t off = (lane_ok & row_ok(y)) ? (uint32_t)(c * plane_sz + wrap(y) * pitch + lane_elem) * kRaw : kBufOOB;
         return buf_load_pair<St>(rs, off);
     };
     auto cs_of = [&](Pair p, int y, int par) -> RowCS<F> {
@@ -739,9 +759,16 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
         const bool ex0 = exists(y, o, 0), ex1 = exists(y, o, 1);
         const bool fr0 = ex0 & !St::sample(old.a);
         const bool fr1 = ex1 & !St::sample(old.b);
-        const U4 r = philox10(U4{(uint32_t)(wrap(y) * np + jj), sweep, (uint32_t)g.chain_word,
+        // inference variants: the key words pass through an empty scalar-register asm, so the
+        // compiler derives the round keys anew (scalar adds) at every call; hoisted out of the
+        // row loop, the 20 round keys do not fit in scalar registers beside the energy sums'
+        // state, and each call would reload them from VGPR lanes with VALU instructions (the
+        // other variants keep them in scalar registers)
+        uint32_t k0 = a.key0, k1 = a.key1;
+        if constexpr ((FLAGS & F_ENERGY) != 0) __asm__ volatile("" : "+s"(k0), "+s"(k1));
+        const U4 r = philox10(U4{(uint32_t)(wrap(y) * np + lane_ctr), sweep, (uint32_t)g.chain_word,
                                  (uint32_t)c},
-                              a.key0, a.key1);
+                              k0, k1);
         const F u0 = St::template value<F>(old.a);
         const F u1 = St::template value<F>(old.b);
         const SiteOut<S, F> o0 = hybrid_update<S, F>(u0, fr0, C0, S0, q, inv_piq, J, kexp, alpha, r.x, r.y);
@@ -767,67 +794,57 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
     // loaded
     auto load_ahead = [&](int c, int y) -> Pair { return (y <= yb + 1) ? load_pair(c, y) : Pair{0, 0}; };
 
-    // stores row y of both colours (new colour-0 pair n0 with its decisions, new colour-1 pair
-    // n1) and accumulates the per-row outputs
-    auto finish_row = [&](int y, int par, const Pair& n0, int d0a, int d0b, const Pair& n1, int d1a,
-                          int d1b, F e) {
-        // non-output lanes address past the resources: their stores are dropped
-        const uint32_t r0 = (uint32_t)(y * pitch + col);
-        const uint32_t r1 = (uint32_t)plane_sz + r0;
-        buf_store_pair<St>(rd, out_lane ? r0 * kRaw : kBufOOB, n0);
-        buf_store_pair<St>(rd, out_lane ? r1 * kRaw : kBufOOB, n1);
-        n_acc += out_lane ? ((d0a >> 1) & 1) + ((d0b >> 1) & 1) + ((d1a >> 1) & 1) + ((d1b >> 1) & 1) : 0;
-        if (FLAGS & F_ENERGY) {
-            const F eo = out_lane ? e : (F)0;
+    // stores the new colour-c pair nv of row y (parity par = (y + c) & 1) with its decisions
+    // da, db and accumulates the per-row outputs; keep (wave-uniform) says whether y is one of
+    // the item's output rows.  The memory operations are issued either way (non-output lanes and
+    // rows address past the resources, so their stores are dropped): every path through the
+    // row loop then has the same count of stores behind the loads, and the compiler can wait for
+    // the loads alone.
+    auto finish = [&](int c, int y, int par, bool keep, const Pair& nv, int da, int db, F e)
+        __attribute__((always_inline)) {
+        const bool on = keep & out_lane;
+        const uint32_t r = (uint32_t)(c * plane_sz + y * pitch + lane_elem);
+        buf_store_pair<St>(rd, on ? r * kRaw : kBufOOB, nv);
+        n_acc += on ? ((da >> 1) & 1) + ((db >> 1) & 1) : 0;
+        if ((FLAGS & F_ENERGY) && c == 1) {
+            const F eo = on ? e : (F)0;
             if (ESINGLE) e_flt += (float)eo;
             else { const Fix2 f = fixed64x2((double)eo); e_hi += f.hi; e_lo += f.lo; }
         }
         if (FLAGS & F_ACC) {
             // compact accumulators: the ranks of this lane's prediction sites (member 1 follows
-            // member 0 when both are prediction sites: 2 jj is even, so both share a mask block)
+            // member 0 when both are prediction sites: 2 jj is even, so both share a mask block);
+            // lanes and rows without output look up row 0, column 0 (halo lanes' columns and
+            // halo rows may lie outside the grid)
             const Rsrc ra = make_rsrc(a.acc + g.site_off, (uint32_t)(it.H * it.W) * 8u);
-            const bool f0a = out_lane & exists(y, par, 0) & !St::sample(n0.a);
-            const bool f0b = out_lane & exists(y, par, 1) & !St::sample(n0.b);
-            const bool f1a = out_lane & exists(y, par ^ 1, 0) & !St::sample(n1.a);
-            const bool f1b = out_lane & exists(y, par ^ 1, 1) & !St::sample(n1.b);
-            const int ck = out_lane ? col : 0;          // halo lanes' columns may lie outside the grid
-            const int64_t k0 = acc_rank(a.rk_mask, a.rk_base, g.rk_off, pitch, 0, y, ck);
-            const int64_t k1 = acc_rank(a.rk_mask, a.rk_base, g.rk_off, pitch, 1, y, ck);
-            const uint32_t o0a = f0a ? (uint32_t)k0 * 8u : kBufOOB, o0b = f0b ? (uint32_t)(k0 + f0a) * 8u : kBufOOB;
-            const uint32_t o1a = f1a ? (uint32_t)k1 * 8u : kBufOOB, o1b = f1b ? (uint32_t)(k1 + f1a) * 8u : kBufOOB;
-            double s0a = buf_load_f64(ra, o0a), s0b = buf_load_f64(ra, o0b);
-            double s1a = buf_load_f64(ra, o1a), s1b = buf_load_f64(ra, o1b);
-            s0a += St::template value<double>(n0.a);
-            s0b += St::template value<double>(n0.b);
-            s1a += St::template value<double>(n1.a);
-            s1b += St::template value<double>(n1.b);
-            buf_store_f64(ra, o0a, s0a);
-            buf_store_f64(ra, o0b, s0b);
-            buf_store_f64(ra, o1a, s1a);
-            buf_store_f64(ra, o1b, s1b);
+            const bool fa = on & exists(y, par, 0) & !St::sample(nv.a);
+            const bool fb = on & exists(y, par, 1) & !St::sample(nv.b);
+            const int64_t kr = acc_rank(a.rk_mask, a.rk_base, g.rk_off, pitch, c, on ? y + yoff : 0, on ? col : 0);
+            const uint32_t oa = fa ? (uint32_t)kr * 8u : kBufOOB, ob = fb ? (uint32_t)(kr + fa) * 8u : kBufOOB;
+            double sa = buf_load_f64(ra, oa), sb = buf_load_f64(ra, ob);
+            sa += St::template value<double>(nv.a);
+            sb += St::template value<double>(nv.b);
+            buf_store_f64(ra, oa, sa);
+            buf_store_f64(ra, ob, sb);
         }
-        if ((FLAGS & F_DEC) && out_lane) {
-            uint8_t* d = a.dec + g.site_off + (int64_t)y * g.W;
-            const int xb = 4 * jj;
-            const int o0 = y & 1, o1 = (y + 1) & 1;
-            if (exists(y, par, 0)) d[xb + o0] = (uint8_t)d0a;
-            if (exists(y, par, 1)) d[xb + 2 + o0] = (uint8_t)d0b;
-            if (exists(y, par ^ 1, 0)) d[xb + o1] = (uint8_t)d1a;
-            if (exists(y, par ^ 1, 1)) d[xb + 2 + o1] = (uint8_t)d1b;
+        if ((FLAGS & F_DEC) && on) {
+            uint8_t* d = a.dec + g.site_off + (int64_t)(y + yoff) * g.W + 4 * jj + par;
+            if (exists(y, par, 0)) d[0] = (uint8_t)da;
+            if (exists(y, par, 1)) d[2] = (uint8_t)db;
         }
     };
 
     // Skewed pipeline: iteration k updates colour 0 at row k and colour 1 at row k - 2.  The two
     // updates share no data (colour 1 at row k - 2 needs the new colour 0 of rows k - 3 ... k - 1
     // only), so in the steady state they form one branch-free block the scheduler interleaves:
-    // twice the independent work per wave of a one-row lag.
+    // twice the independent work per wave of a one-row lag.  Both new rows are stored at the end
+    // of their iteration (colour 1 first, measured 3 % faster than the other order), so no new
+    // row is carried from one iteration to the next.
     // window: colour-1 old raw rows k-2 ... k+1 and (cos, sin) rows k-1 ... k+1; colour-0 new
-    // (cos, sin) rows k-3 ... k, raw rows and decisions k-2 ... k
+    // (cos, sin) rows k-3 ... k
     Pair v0_cur, v0_next, r1_m2, r1_m1 = Pair{0, 0}, r1_0, r1_p1;
     RowCS<F> w1_m1, w1_0, w1_p1;
     RowCS<F> w0_m3, w0_m2 = zero, w0_m1 = zero, w0_0 = zero;
-    Pair n0_m2, n0_m1 = Pair{0, 0}, n0_0 = Pair{0, 0};
-    int d0_m2a, d0_m2b, d0_m1a = 0, d0_m1b = 0, d0_0a = 0, d0_0b = 0;
 
     r1_0 = load_pair(1, ya - 2);
     w1_0 = cs_of(r1_0, ya - 2, (ya - 1) & 1);
@@ -847,8 +864,6 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
         w1_m1 = w1_0; w1_0 = w1_p1;
         r1_m2 = r1_m1; r1_m1 = r1_0; r1_0 = r1_p1;
         w0_m3 = w0_m2; w0_m2 = w0_m1; w0_m1 = w0_0;
-        n0_m2 = n0_m1; n0_m1 = n0_0;
-        d0_m2a = d0_m1a; d0_m2b = d0_m1b; d0_m1a = d0_0a; d0_m1b = d0_0b;
         v0_cur = v0_next;
         r1_p1 = pf1[0];
         v0_next = pf0[0];
@@ -859,38 +874,30 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
         }
         pf1[kPrefetchRows - 1] = load_ahead(1, k + 1 + kPrefetchRows);
         pf0[kPrefetchRows - 1] = load_ahead(0, k + 1 + kPrefetchRows);
+        Pair n0;
+        int d0a, d0b;
         if (do_c0) w1_p1 = cs_of(r1_p1, k + 1, par);
         if (do_c0 && (!c0_rows_checked || row_ok(k))) {
             F e_unused;
-            update_row(v0_cur, w1_m1, w1_0, w1_p1, k, 0, par, n0_0, w0_0, d0_0a, d0_0b, e_unused);
+            update_row(v0_cur, w1_m1, w1_0, w1_p1, k, 0, par, n0, w0_0, d0a, d0b, e_unused);
         } else {
-            n0_0 = v0_cur;
+            n0 = v0_cur;
             w0_0 = zero;
-            d0_0a = d0_0b = 0;
+            d0a = d0b = 0;
         }
+        Pair n1;
+        int d1a, d1b;
+        F e;
         if (do_c1) {
-            const int y = k - 2;
-            Pair n1;
             RowCS<F> cs1;
-            int d1a, d1b;
-            F e;
-            update_row(r1_m2, w0_m3, w0_m2, w0_m1, y, 1, par ^ 1, n1, cs1, d1a, d1b, e);
-            finish_row(y, par, n0_m2, d0_m2a, d0_m2b, n1, d1a, d1b, e);
+            update_row(r1_m2, w0_m3, w0_m2, w0_m1, k - 2, 1, par ^ 1, n1, cs1, d1a, d1b, e);
         } else {
-            // the same memory operations, all out of range: every path into the steady loop
-            // then has the same count of stores behind the loads, and the compiler can wait for
-            // the loads alone
-            buf_store_pair<St>(rd, kBufOOB, Pair{0, 0});
-            buf_store_pair<St>(rd, kBufOOB, Pair{0, 0});
-            if (FLAGS & F_ACC) {
-                const Rsrc ra = make_rsrc(a.acc + g.site_off, (uint32_t)(it.H * it.W) * 8u);
-                double s[4];
-#pragma unroll
-                for (int m = 0; m < 4; ++m) s[m] = buf_load_f64(ra, kBufOOB);
-#pragma unroll
-                for (int m = 0; m < 4; ++m) buf_store_f64(ra, kBufOOB, s[m]);
-            }
+            n1 = Pair{0, 0};
+            d1a = d1b = 0;
+            e = (F)0;
         }
+        finish(1, k - 2, par ^ 1, do_c1, n1, d1a, d1b, e);
+        finish(0, k, par, do_c0 & (k >= ya) & (k < yb), n0, d0a, d0b, (F)0);
     };
     // fill: colour 0 only (rows ya-1 ... ya+1); steady state: both colours, rows in the grid;
     // drain: colour 0 of row yb (if in the grid) and colour 1 of the last two rows

@@ -143,6 +143,32 @@ def test_fp64_tiny_and_ragged_grids_match_oracle(mpr, H, W, boundary, chains, mo
     assert n_checked > 0
 
 
+
+@pytest.mark.parametrize("H,W,boundary,rows", [
+    (12, 40, 0, 2), (13, 280, 0, 2), (19, 112, 0, 4), (11, 113, 0, 2), (16, 112, 1, 2),
+    (24, 280, 1, 4), (13, 40, 0, 3), (10, 40, 1, 2), (9, 40, 0, 2)])
+def test_fp64_two_half_items_match_oracle(mpr, H, W, boundary, rows):
+    """Fused sweeps whose last column strip (at most 28 lane pairs) is swept by half waves, two
+    inner row blocks per wave (blocks 1, 2 | 3, 4 | ... while both halves' halo rows lie in the
+    grid): one strip (W = 40), a last strip after a full one (W = 280), exactly 28 pairs
+    (W = 112), 29 pairs (W = 113, one item per block), an odd row count (rows = 3, one item per
+    block), too few rows for a pair (9 x 40), ragged last row blocks, periodic grids.  Every
+    decision and angle agrees with the oracle except where the local field vanishes (see
+    _degenerate_sites)."""
+    _LAST_BEFORE.clear()
+    mask, rounds = _decisions_case(mpr, H, W, boundary, 2, mpr.FP64, seed=H * 11 + W + rows,
+                                   mode=1, tile_rows=rows)
+    free = np.broadcast_to(mask == 0, rounds[0][0].shape)
+    n_checked = 0
+    for (dg, do, ug, uo), before in zip(rounds, _LAST_BEFORE):
+        uo = uo.reshape(dg.shape)
+        assert np.array_equal(dg[~free], do[~free]) and not dg[~free].any()
+        ok = free & ~_degenerate_sites(mask, before, uo, boundary)
+        assert np.array_equal(dg[ok], do[ok])
+        assert np.allclose(ug[ok], uo[ok], rtol=0, atol=1e-9)
+        n_checked += int(ok.sum())
+    assert n_checked > 0
+
 def test_fp64_trace_matches_oracle(mpr):
     """Per-sweep (e_sim, T, alpha, acceptance) of the temperature inference."""
     truth, z, mask = _field(64, 64, 1)
