@@ -6,8 +6,9 @@ HBM: load (validation, data map, sample energy, initial state), temperature infe
 second over the whole step: one site update = one hybrid (over-relaxation + Metropolis) update
 of one prediction site in one sweep of one chain.
 
-The default workload is the batch of 256 grids (sides 64 ... 1024, four chains each) with FP32
-angle storage and FP32 functions: the reduced-precision batched path.
+The default workload is the batch of 256 grids (sides 64 ... 1024, four chains each) with FP16
+angle storage and FP32 functions and arithmetic: the reduced-precision batched path (its FP32
+storage, FP64 and 1024^2 setups follow in `setups`).
 
 Also printed in the same JSON line:
   roofline      the inference sweep kernel (its average launch time from HIP events on the
@@ -356,7 +357,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batch256", choices=sorted(SWEEPS))
-    ap.add_argument("--precision", default="fp32", choices=sorted(PREC))
+    ap.add_argument("--precision", default="fp16", choices=sorted(PREC))
     ap.add_argument("--p-missing", type=float, default=None)
     ap.add_argument("--sweep-mode", default="auto", choices=sorted(SWEEP_MODE),
                     help="sweep path: automatic choice, fused row blocks, compacted site lists, or LDS tiles")

@@ -95,7 +95,11 @@ typedef struct mpr_config {
                                  autotuner with tile_rows = -1), 1 + mpr_tile_shape
                                  forces one (all but MPR_TILE_W4_BASE need
                                  single-precision functions, EINVAL otherwise)        */
-    int32_t reserved[4];
+    int32_t group_waves;      /* compacted path: list waves (64 prediction sites each) one
+                                 wave sweeps per launch, 1 ... 32; 0 = automatic (as
+                                 many as keep about 20 480 groups per colour, at most
+                                 32); results do not depend on it                     */
+    int32_t reserved[3];
 } mpr_config;
 
 /* Block shapes of the tiled path: waves per block and tile height (the base height is 16 rows,
@@ -108,8 +112,8 @@ typedef enum mpr_tile_shape {
  * FUSED: one launch per sweep over every site in row blocks, both colours in one pass with halo
  *   recomputation; best when most sites are prediction sites and the grid is large.
  * SPARSE: two launches per sweep (one per colour) over lists of the prediction sites only, built
- *   at load; needs double-precision energy and grids with H < 65536 and
- *   ceil(ceil(W / 2) / 2) * 2 < 65536.
+ *   at load, one wave per group of up to group_waves list waves of one (grid, chain); needs
+ *   double-precision energy and grids with H < 65536 and ceil(ceil(W / 2) / 2) * 2 < 65536.
  * TILED: one launch per sweep, one block per tile of 128 columns staged in LDS with its halo
  *   (the block shape, mpr_tile_shape, unless forced or tuned: eight-wave blocks on tiles of 32
  *   rows, 16 with 8-byte spins, while the grids hold fewer than 2048 tiles of half that height;

@@ -855,10 +855,12 @@ struct mpr_ctx {
     bool sparse = false;
     uint32_t* d_sites = nullptr;
     int64_t sites_cap = 0;
-    int2* d_waves[2] = {nullptr, nullptr};
+    int4* d_waves[2] = {nullptr, nullptr};                   // groups: (gc, first entry, list waves, 0)
     int32_t* d_lead[2] = {nullptr, nullptr};
     int64_t waves_cap[2] = {0, 0};
-    int32_t n_waves[2] = {0, 0};
+    int32_t n_waves[2] = {0, 0};                             // groups per colour
+    int32_t list_waves[2] = {0, 0};                          // 64-entry list waves per colour
+    int32_t group_waves = 1;                                 // list waves per group (at most)
     int64_t list_base0[2] = {0, 0};                          // grid 0's list starts
     int64_t* d_econst = nullptr;                             // [n_gc][2]
     int32_t* d_rowcnt = nullptr;                             // scratch of the list build
@@ -924,6 +926,7 @@ static int check_config(const mpr_config* c)
     if (c->tile_rows < -1 || c->grid_offset < 0) return MPR_EINVAL;
     if (c->sweep_mode < MPR_SWEEP_AUTO || c->sweep_mode > MPR_SWEEP_TILED) return MPR_EINVAL;
     if (c->tile_shape < 0 || c->tile_shape > kTileShapes) return MPR_EINVAL;
+    if (c->group_waves < 0 || c->group_waves > kMaxGroupWaves) return MPR_EINVAL;
     if ((c->sweep_mode == MPR_SWEEP_SPARSE || c->sweep_mode == MPR_SWEEP_TILED) &&
         c->energy_prec == MPR_PREC_SINGLE)
         return MPR_EINVAL;
@@ -1316,16 +1319,32 @@ static int build_lists(mpr_ctx* c)
         meta[G + i] = entries;
         entries += std::max<int64_t>(1, (tot[i] + kWave - 1) / kWave) * kWave;
     }
-    std::vector<int2> waves[2];
+    // A compacted-path wave sweeps a group of up to group_waves consecutive list waves of one
+    // (grid, chain), so the per-wave work (control step, reductions, atomics, the first loads)
+    // is shared by up to group_waves x 64 sites; groups stay numerous enough to fill the chip
+    // (about 20 480 per colour, two and a half rounds of eight resident waves per SIMD) before
+    // they grow (measured on the 256-grid batch in FP16: 4, 8, 16, 32, 64, 128 list waves per
+    // group gave 1.205, 1.024, 0.942, 0.917, 0.934, 0.968 ms per sweep).
+    int64_t lw_total = 0;
+    for (int i = 0; i < n_gc; ++i)
+        for (int col = 0; col < 2; ++col)
+            lw_total += std::max<int64_t>(1, ((int64_t)tot[2 * c->gcs[i].grid + col] + kWave - 1) / kWave);
+    const int ns = c->cfg.group_waves > 0
+                       ? c->cfg.group_waves
+                       : (int)std::min<int64_t>(kMaxGroupWaves, std::max<int64_t>(1, lw_total / 2 / kGroupTarget));
+    std::vector<int4> waves[2];
     std::vector<int32_t> lead[2];
+    int32_t list_waves[2] = {0, 0};
     for (int col = 0; col < 2; ++col) {
         lead[col].resize(n_gc);
         for (int i = 0; i < n_gc; ++i) {
             const int gr = c->gcs[i].grid;
             const int64_t nw = std::max<int64_t>(1, ((int64_t)tot[2 * gr + col] + kWave - 1) / kWave);
             lead[col][i] = (int32_t)waves[col].size();
-            for (int64_t w = 0; w < nw; ++w)
-                waves[col].push_back(int2{i, (int)(meta[G + 2 * gr + col] + w * kWave)});
+            for (int64_t w = 0; w < nw; w += ns)
+                waves[col].push_back(int4{i, (int)(meta[G + 2 * gr + col] + w * kWave),
+                                          (int)std::min<int64_t>(ns, nw - w), 0});
+            if (i == 0) list_waves[col] = (int32_t)std::min<int64_t>(nw, INT32_MAX);
         }
         if (waves[col].size() > (size_t)INT32_MAX / kWavesPerBlock)
             return fail(c, MPR_EINVAL, "too many prediction sites for the compacted path");
@@ -1334,12 +1353,16 @@ static int build_lists(mpr_ctx* c)
     // captured sweeps hold the wave counts and list bases in their arguments: a reload with the
     // same shapes but other lists must capture again
     if (meta[G] != c->list_base0[0] || meta[G + 1] != c->list_base0[1] ||
-        (int64_t)waves[0].size() != c->n_waves[0] || (int64_t)waves[1].size() != c->n_waves[1]) {
+        (int64_t)waves[0].size() != c->n_waves[0] || (int64_t)waves[1].size() != c->n_waves[1] ||
+        ns != c->group_waves || list_waves[0] != c->list_waves[0] || list_waves[1] != c->list_waves[1]) {
         for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
         c->graphs.clear();
     }
     c->list_base0[0] = meta[G];
     c->list_base0[1] = meta[G + 1];
+    c->group_waves = ns;
+    c->list_waves[0] = list_waves[0];
+    c->list_waves[1] = list_waves[1];
     rc = ensure_buffer(c, (void**)&c->d_sites, &c->sites_cap, entries * 4);
     if (rc) return rc;
     HIPCHK(c, hipMemsetAsync(c->d_sites, 0xff, entries * 4, c->stream));
@@ -1352,11 +1375,11 @@ static int build_lists(mpr_ctx* c)
     }
     for (int col = 0; col < 2; ++col) {
         c->n_waves[col] = (int32_t)waves[col].size();
-        rc = ensure_buffer(c, (void**)&c->d_waves[col], &c->waves_cap[col], (int64_t)waves[col].size() * sizeof(int2));
+        rc = ensure_buffer(c, (void**)&c->d_waves[col], &c->waves_cap[col], (int64_t)waves[col].size() * sizeof(int4));
         if (rc) return rc;
         rc = ensure_buffer(c, (void**)&c->d_lead[col], &c->lead_cap[col], (int64_t)n_gc * sizeof(int32_t));
         if (rc) return rc;
-        HIPCHK(c, h2d(c, c->d_waves[col], waves[col].data(), waves[col].size() * sizeof(int2)));
+        HIPCHK(c, h2d(c, c->d_waves[col], waves[col].data(), waves[col].size() * sizeof(int4)));
         HIPCHK(c, h2d(c, c->d_lead[col], lead[col].data(), n_gc * sizeof(int32_t)));
     }
     return build_econst(c);
@@ -1775,6 +1798,8 @@ static void enqueue_sparse(mpr_ctx* c, int flags, int sweep_off, const RunCtl* r
         a.key1 = (uint32_t)(c->cfg.seed >> 32);
         a.single = c->gcs.size() == 1;
         a.single_base = c->list_base0[col];
+        a.group_waves = c->group_waves;
+        a.single_waves = c->list_waves[col];
         const unsigned blocks = (unsigned)((c->n_waves[col] + kWavesPerBlock - 1) / kWavesPerBlock);
         hipLaunchKernelGGL(sparse_fn(c, flags, col), dim3(blocks), dim3(kWave * kWavesPerBlock), 0,
                            c->stream, a);

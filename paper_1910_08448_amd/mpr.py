@@ -34,7 +34,8 @@ class mpr_config(ctypes.Structure):
                 ("acc_target", ctypes.c_double), ("T_min", ctypes.c_double),
                 ("T_max", ctypes.c_double), ("tile_rows", ctypes.c_int32),
                 ("graph_sweeps", ctypes.c_int32), ("sweep_mode", ctypes.c_int32),
-                ("tile_shape", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("tile_shape", ctypes.c_int32), ("group_waves", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class mpr_timings(ctypes.Structure):

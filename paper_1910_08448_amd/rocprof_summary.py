@@ -129,6 +129,18 @@ def valu(d, updates):
         tr = m.get("SQ_INSTS_VALU_TRANS_F32", 0.0) * 64.0 / updates if k in ("fused", "tiled") else float("nan")
         out.append("| %s | %d | %.4g | %.3f | %.3f | %.3f | %.3f | %.1f | %.2f |" % (
             k, n, m.get("SQ_INSTS_VALU", 0.0), rate, rate, rate / 2.0, act2 / act if act else 0.0, per_upd, tr))
+    # the compacted path's sweep is its two colour kernels: per update, their sums
+    if "sparse0" in agg and "sparse1" in agg:
+        tot = {c: sum(sum(agg[k][c]) / len(agg[k][c]) for k in ("sparse0", "sparse1") if agg[k].get(c))
+               for c in ("SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_VALU2",
+                         "SQ_INSTS_VALU_TRANS_F32", "GRBM_GUI_ACTIVE")}
+        act, act2 = tot["SQ_ACTIVE_INST_VALU"], tot["SQ_ACTIVE_INST_VALU2"]
+        quads = tot["GRBM_GUI_ACTIVE"] / N_XCD / 4.0
+        rate = act / (N_SIMD * quads) if quads else float("nan")
+        n = min(len(agg["sparse0"].get("SQ_INSTS_VALU", [])), len(agg["sparse1"].get("SQ_INSTS_VALU", [])))
+        out.append("| sparse0 + sparse1 (one sweep) | %d | %.4g | %.3f | %.3f | %.3f | %.3f | %.1f | %.2f |" % (
+            n, tot["SQ_INSTS_VALU"], rate, rate, rate / 2.0, act2 / act if act else 0.0,
+            act * 64.0 / updates, tot["SQ_INSTS_VALU_TRANS_F32"] * 64.0 / updates))
     return "\n".join(out)
 
 

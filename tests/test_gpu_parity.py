@@ -324,7 +324,7 @@ def test_gpu_error_codes(mpr):
     m = np.ones((4, 4), np.uint8)
     m[1, 1] = 0
     for kw in [dict(q=0.6), dict(J=-1.0), dict(n_chains=0), dict(precision=7),
-               dict(precision=2, func_prec=0)]:
+               dict(precision=2, func_prec=0), dict(group_waves=-1), dict(group_waves=33)]:
         with pytest.raises(mpr.MprError) as e:
             mpr.Context(**kw)
         assert e.value.code == mpr.EINVAL
@@ -657,6 +657,39 @@ def test_tiled_equals_sparse_bitwise(mpr, precision, func_prec, p):
             assert np.array_equal(a, b)
         assert np.array_equal(res[0][2], res[1][2])
 
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_sparse_group_sizes_are_bitwise_equal(mpr, precision):
+    """A compacted-path wave sweeps a group of up to group_waves list waves of one (grid, chain):
+    whole runs (temperature trajectories, estimates, predictions, the averaging sweeps' running
+    sums) agree bit for bit with one list wave per group, for groups of 2, 3, 7 and 32 list
+    waves (uneven tails and (grid, chain)s with fewer list waves than a group), and the
+    decisions of a single sweep too; a batch of uneven grids with two chains, and one grid."""
+    cases = [([(45, 70), (17, 300), (2, 3), (130, 244), (64, 64)], 2), ([(200, 340)], 1)]
+    for shapes, chains in cases:
+        fields = [_field(h, w, 700 + i) for i, (h, w) in enumerate(shapes)]
+        z = np.concatenate([f[1].ravel() for f in fields])
+        m = np.concatenate([f[2].ravel() for f in fields])
+        res = []
+        for gw in (1, 2, 3, 7, 32):
+            ctx = mpr.Context(shapes=shapes, stream=torch.cuda.Stream(), seed=5, n_chains=chains,
+                              precision=precision, sweep_mode=mpr.SWEEP_SPARSE, group_waves=gw)
+            ctx.batch_load(_dev(z, torch.float64), _dev(m, torch.uint8))
+            T = ctx.infer_temperature(20)
+            tr = [ctx.trace(i) for i in range(chains * len(shapes))]
+            ctx.run(5)
+            pred = ctx.predictions().cpu().numpy()
+            st = ctx.get_state()
+            dec = ctx.debug_sweep(77).cpu().numpy()
+            res.append((T, tr, pred, st["u"].cpu().numpy(), st["acc"].cpu().numpy(), dec))
+        for r in res[1:]:
+            assert np.array_equal(res[0][0], r[0])
+            for a, b in zip(res[0][1], r[1]):
+                assert np.array_equal(a, b)
+            for i in (2, 3, 4, 5):
+                assert np.array_equal(res[0][i], r[i])
+        assert (res[0][5] & mpr.DEC_ACCEPT).any()
 
 @pytest.mark.parametrize("mode", [1, 2, 3])
 @pytest.mark.parametrize("p_first,p_second", [(0.3, 0.6), (0.6, 0.3)])
