@@ -665,16 +665,19 @@ def test_sparse_group_sizes_are_bitwise_equal(mpr, precision):
     whole runs (temperature trajectories, estimates, predictions, the averaging sweeps' running
     sums) agree bit for bit with one list wave per group, for groups of 2, 3, 7 and 32 list
     waves (uneven tails and (grid, chain)s with fewer list waves than a group), and the
-    decisions of a single sweep too; a batch of uneven grids with two chains, and one grid."""
-    cases = [([(45, 70), (17, 300), (2, 3), (130, 244), (64, 64)], 2), ([(200, 340)], 1)]
-    for shapes, chains in cases:
+    decisions of a single sweep too; a batch of uneven open grids with two chains, a periodic
+    batch, and one grid."""
+    cases = [([(45, 70), (17, 300), (2, 3), (130, 244), (64, 64)], 2, 0),
+             ([(16, 24), (34, 264), (96, 128)], 2, 1), ([(200, 340)], 1, 0)]
+    for shapes, chains, boundary in cases:
         fields = [_field(h, w, 700 + i) for i, (h, w) in enumerate(shapes)]
         z = np.concatenate([f[1].ravel() for f in fields])
         m = np.concatenate([f[2].ravel() for f in fields])
         res = []
         for gw in (1, 2, 3, 7, 32):
             ctx = mpr.Context(shapes=shapes, stream=torch.cuda.Stream(), seed=5, n_chains=chains,
-                              precision=precision, sweep_mode=mpr.SWEEP_SPARSE, group_waves=gw)
+                              precision=precision, sweep_mode=mpr.SWEEP_SPARSE, group_waves=gw,
+                              boundary=boundary)
             ctx.batch_load(_dev(z, torch.float64), _dev(m, torch.uint8))
             T = ctx.infer_temperature(20)
             tr = [ctx.trace(i) for i in range(chains * len(shapes))]
