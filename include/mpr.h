@@ -128,9 +128,10 @@ typedef enum mpr_tile_shape {
  * (small grids, where a sweep is bound by latency: one launch instead of two) and either the
  * functions are evaluated in single precision or more than 60 % of the sites are prediction
  * sites; otherwise SPARSE when it is possible and either the functions are evaluated in double
- * precision with at most 60 % prediction sites and sites x chains <= 2^25 or at most 70 % and
- * sites x chains <= 2^23, or in single precision with at most 40 % prediction sites and
- * sites x chains <= 2^23 (measured crossovers on MI355X); FUSED otherwise.  The choice depends on the loaded data and
+ * precision with at most 60 % prediction sites, or at most 70 % and sites x chains <= 2^23, or
+ * the angles are stored in 16 bits with at most 50 % prediction sites, or in FP32 with at most
+ * 40 % prediction sites and sites x chains <= 2^23 (measured crossovers on MI355X); FUSED
+ * otherwise.  The choice depends on the loaded data and
  * configuration only (or, with tile_rows = -1, on the autotuner's timing) and is fixed for the
  * context until the next load. */
 typedef enum mpr_sweep_mode {

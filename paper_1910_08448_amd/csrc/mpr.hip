@@ -1430,8 +1430,12 @@ static int auto_path(const mpr_ctx* c)
     // no list reads): small grids with single-precision functions, and with double-precision
     // functions once most sites are prediction sites
     if (tiled_possible(c) && work <= 1572864.0 && (c->fsingle || frac > 0.6)) return MPR_SWEEP_TILED;
-    const bool prefer = c->fsingle ? (frac <= 0.4 && work <= 8388608.0)
-                                   : ((frac <= 0.6 && work <= 33554432.0) || (frac <= 0.7 && work <= 8388608.0));
+    // the compacted path in groups: with 16-bit storage it beats the fused kernel once half the
+    // sites or fewer are prediction sites (batch of 256 grids at 43 %: 0.93 against 1.19 ms per
+    // sweep; 16384^2 at 50 %: 0.72 against 0.75 ms); with double-precision functions up to 60 %
+    // at any size; with FP32 storage its doubled bytes stall it beyond small grids
+    const bool prefer = c->fsingle ? (c->elem == 2 ? frac <= 0.5 : (frac <= 0.4 && work <= 8388608.0))
+                                   : (frac <= 0.6 || (frac <= 0.7 && work <= 8388608.0));
     return (sparse_possible(c) && prefer) ? MPR_SWEEP_SPARSE : MPR_SWEEP_FUSED;
 }
 

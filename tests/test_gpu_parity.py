@@ -534,9 +534,10 @@ def test_sparse_batch_equals_single_grids(mpr, mode):
 
 def test_automatic_path_choice(mpr):
     """AUTO takes the tiled path for small grids with single-precision functions or with
-    double-precision functions and mostly prediction sites, the compacted path for small grids
-    with fewer prediction sites and double-precision functions, when the energy is summed in
-    double precision; the fused path otherwise."""
+    double-precision functions and mostly prediction sites, the compacted path with fewer
+    prediction sites (at any size with double-precision functions or 16-bit storage, on small
+    grids with FP32 storage), when the energy is summed in double precision; the fused path
+    otherwise."""
     for p, prec, esingle, want in [(0.33, mpr.FP32, False, mpr.SWEEP_TILED),
                                    (0.5, mpr.FP16, False, mpr.SWEEP_TILED),
                                    (0.5, mpr.FP64, False, mpr.SWEEP_SPARSE),
@@ -555,13 +556,20 @@ def test_automatic_path_choice(mpr):
         mask = (rng.random((side, side)) >= p).astype(np.uint8)
         z = np.where(mask == 1, rng.standard_normal((side, side)), np.nan)
         assert _gpu_ctx(mpr, z, mask, precision=mpr.FP32).sweep_mode() == want, (side, p)
-    # double-precision functions past the tiled limit: compacted up to 70 % prediction sites and
-    # 2^23 sites, else fused
+    # double-precision functions past the tiled limit: compacted up to 60 % prediction sites at
+    # any size and up to 70 % with 2^23 sites, else fused
     for side, p, want in [(2048, 0.66, mpr.SWEEP_SPARSE), (2048, 0.9, mpr.SWEEP_FUSED),
-                          (4096, 0.66, mpr.SWEEP_FUSED)]:
+                          (4096, 0.66, mpr.SWEEP_FUSED), (4096, 0.5, mpr.SWEEP_SPARSE)]:
         mask = (rng.random((side, side)) >= p).astype(np.uint8)
         z = np.where(mask == 1, rng.standard_normal((side, side)), np.nan)
         assert _gpu_ctx(mpr, z, mask, precision=mpr.FP64).sweep_mode() == want, (side, p)
+    # 16-bit storage past the tiled limit: compacted up to 50 % prediction sites at any size
+    for side, p, prec, want in [(2048, 0.45, mpr.FP16, mpr.SWEEP_SPARSE),
+                                (4096, 0.45, mpr.FIX16, mpr.SWEEP_SPARSE),
+                                (2048, 0.6, mpr.FP16, mpr.SWEEP_FUSED)]:
+        mask = (rng.random((side, side)) >= p).astype(np.uint8)
+        z = np.where(mask == 1, rng.standard_normal((side, side)), np.nan)
+        assert _gpu_ctx(mpr, z, mask, precision=prec).sweep_mode() == want, (side, p, prec)
     truth, z, mask = _field(64, 64, 5)
     for mode in (mpr.SWEEP_SPARSE, mpr.SWEEP_TILED):
         with pytest.raises(mpr.MprError):
