@@ -639,16 +639,16 @@ template <class F> struct RowCS { F c0, s0, c1, s1; };
 
 // ------------------------------------------------------------------ fused sweep kernel
 // One wave = one work item: 64 lanes hold pairs pair0-2 .. pair0+61 of one (grid, chain);
-// lanes 2..61 are output lanes.  A two-half item (dy > 0) holds pairs pair0-2 .. pair0+29 in
-// each half, output lanes 2..29 of the half, the upper half dy rows further down: the ragged
-// last strips of two row blocks then fill one wave.  The wave walks the rows k of the lower
-// half; the upper half's row is k + dy, which enters only the lanes' address and counter
-// offsets: every row of a two-half item lies inside the grid, so the row tests (and the
-// periodic wrap) stay the same for both halves and wave-uniform.  The wave walks down rows y0-2 .. y1+1 keeping a 3-row window:
+// lanes 2..61 are output lanes.  The wave walks down rows y0-2 .. y1+1 keeping a 3-row window:
 // the old colour-1 (cos, sin) feed the colour-0 update of the middle row, the new colour-0
 // (cos, sin) of three rows feed the colour-1 update one row behind.  Halo lanes and rows
 // repeat their neighbours' colour-0 updates bit for bit (same inputs, same counters), so
 // items never exchange data within a sweep; the sweep reads `src` and writes `dst`.
+// A two-half item (dy > 0) holds pairs pair0-2 .. pair0+29 in each half, output lanes 2..29 of
+// the half, the upper half dy rows further down: the ragged last strips of two row blocks then
+// fill one wave.  Rows k are the lower half's; the upper half's row k + dy enters only the
+// lanes' address and counter offsets: every row of a two-half item lies inside the grid, so the
+// row tests (and the periodic wrap) stay the same for both halves and wave-uniform.
 // Single-precision functions: at least five waves per SIMD (at most 96 VGPRs; the compiler's own
 // choice for some variants is four waves with up to 128), except the averaging variants, which
 // hold an iteration's running sums in flight across its updates (four waves).
