@@ -647,26 +647,27 @@ __global__ __launch_bounds__(256) void k_list_fill(const GcDesc* gcs, int n_chai
     }
 }
 
-// energy of the sample-sample bonds of (grid, chain) blockIdx.y from the stored values, as the
-// compacted path's colour kernels would sum it: per colour-1 sample site, its bonds to colour-0
-// samples, c cos + s sin in the compute precision, two-word fixed point
+// energy of the sample-sample bonds of grid blockIdx.y from the stored values, as the compacted
+// path's colour kernels would sum it: per colour-1 sample site, its bonds to colour-0 samples,
+// c cos + s sin in the compute precision, two-word fixed point.  Sample values are the same in
+// every chain, so the grid's first chain is read and the sum is added to each chain's words.
+// Blocks take rows (grid-stride), threads plane columns: no element index is divided.
 template <class S, class F, bool PER>
-__global__ __launch_bounds__(256) void k_econst(const GcDesc* gcs, const void* st, double q,
-                                                int64_t* econst)
+__global__ __launch_bounds__(256) void k_econst(const GcDesc* gcs, int n_chains, const void* st,
+                                                double q, int64_t* econst)
 {
     using St = Store<S>;
     using M = Math<F>;
     __shared__ int64_t sh[4];
-    const GcDesc g = gcs[blockIdx.y];
+    const GcDesc g = gcs[(int64_t)blockIdx.y * n_chains];
     const typename St::raw* p = (const typename St::raw*)st + g.plane_off;
     const int64_t plane = (int64_t)g.H * g.pitch;
     int64_t e_hi = 0, e_lo = 0;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < plane;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int y = (int)(e / g.pitch), k = (int)(e - (int64_t)y * g.pitch);
+    for (int y = (int)blockIdx.x; y < g.H; y += (int)gridDim.x)
+      for (int k = (int)threadIdx.x; 2 * k < g.W; k += (int)blockDim.x) {
         const int x = 2 * k + ((y + 1) & 1);
         if (x >= g.W) continue;
-        const typename St::raw v = p[plane + e];
+        const typename St::raw v = p[plane + (int64_t)y * g.pitch + k];
         if (!St::sample(v)) continue;
         int xl = x - 1, xr = x + 1, yu = y - 1, yd = y + 1;
         bool el = xl >= 0, er = xr < g.W, eu = yu >= 0, ed = yd < g.H;
@@ -697,8 +698,11 @@ __global__ __launch_bounds__(256) void k_econst(const GcDesc* gcs, const void* s
     e_hi = block_sum256(e_hi, sh);
     e_lo = block_sum256(e_lo, sh);
     if (threadIdx.x == 0) {
-        atomicAdd((unsigned long long*)&econst[2 * blockIdx.y], (unsigned long long)e_hi);
-        atomicAdd((unsigned long long*)&econst[2 * blockIdx.y + 1], (unsigned long long)e_lo);
+        for (int ch = 0; ch < n_chains; ++ch) {
+            const int64_t gc = (int64_t)blockIdx.y * n_chains + ch;
+            atomicAdd((unsigned long long*)&econst[2 * gc], (unsigned long long)e_hi);
+            atomicAdd((unsigned long long*)&econst[2 * gc + 1], (unsigned long long)e_lo);
+        }
     }
 }
 
@@ -1230,11 +1234,12 @@ static void launch_list_fill(mpr_ctx* c, int hmax, const int64_t* row_off, const
 
 template <class S, class F> static void launch_econst(mpr_ctx* c)
 {
-    int64_t plane = 0;
-    for (const auto& d : c->gcs) plane = std::max<int64_t>(plane, (int64_t)d.H * d.pitch);
-    const dim3 grid = site_grid(plane, (int)c->gcs.size(), 1024);
+    int hmax = 1;
+    for (int g = 0; g < c->G; ++g) hmax = std::max<int>(hmax, (int)c->H[g]);
+    const dim3 grid((unsigned)std::min(hmax, 1024), (unsigned)c->G);   // rows x grids
     auto fn = c->cfg.boundary == MPR_PERIODIC ? k_econst<S, F, true> : k_econst<S, F, false>;
-    hipLaunchKernelGGL(fn, grid, dim3(256), 0, c->stream, c->d_gcs, c->d_state[c->cur], c->cfg.q, c->d_econst);
+    hipLaunchKernelGGL(fn, grid, dim3(256), 0, c->stream, c->d_gcs, c->C, c->d_state[c->cur], c->cfg.q,
+                       c->d_econst);
 }
 
 static int build_econst(mpr_ctx* c);
