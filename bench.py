@@ -375,7 +375,7 @@ def main():
                     help="copy a buffer of this many MiB once (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the method on a single MI355X "
+        print("bench.py measures one GPU: the library runs the method on a single MI355X "
               "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
