@@ -906,3 +906,60 @@ def test_timings_report_each_phase(mpr):
     t = ctx.timings()
     assert t["infer_ms"] > 0.0 and t["run_ms"] > 0.0 and t["predict_ms"] > 0.0
     assert t["infer_sweeps"] == 33 and t["run_sweeps"] == 7
+
+
+def _far_rows_field(seed):
+    """300 x 1024 grid whose prediction sites lie in a few rows up to 150 apart (five random
+    sites and the last two columns of each); every other site is a sample."""
+    H, W = 300, 1024
+    truth = synth.gaussian_field(H, W, 0.5, 32.0, 50.0, 10.0, seed)
+    rng = np.random.default_rng(seed)
+    mask = np.ones((H, W), np.uint8)
+    for y in (0, 1, 126, 127, 128, 140, 290, 299):
+        mask[y, rng.choice(W - 2, 5, replace=False)] = 0
+        mask[y, W - 2:] = 0
+    return truth, np.where(mask == 1, truth, np.nan), mask
+
+
+def test_sparse_far_rows_and_wide_grids(mpr):
+    """Compacted-path list waves whose sites lie in rows far apart (a 300 x 1024 grid with
+    prediction sites in eight rows up to 150 apart) and plane rows of thousands of sites (a
+    6 x 40000 grid): from identical states the decisions and angles equal the fused path's bit
+    for bit (FP64, FP16), and whole runs of a batch of both grids equal the tiled path's."""
+    wide = _field(6, 40000, 41)
+    far = _far_rows_field(43)
+    for truth, z, mask in (wide, far):
+        H, W = mask.shape
+        u0 = synth.random_state(2, mask, 9)
+        for precision in (mpr.FP64, mpr.FP16):
+            out = []
+            for mode in (mpr.SWEEP_FUSED, mpr.SWEEP_SPARSE):
+                ctx = _gpu_ctx(mpr, z, mask, precision=precision, sweep_mode=mode, n_chains=2,
+                               seed=3, alpha0=0.5)
+                assert ctx.sweep_mode() == mode
+                ctx.set_state(u=_dev(u0.reshape(-1), torch.float64))
+                ctx.set_temperature(0.05)
+                decs = [ctx.debug_sweep(s).cpu().numpy() for s in (4, 5, 6)]
+                out.append((decs, ctx.get_state()["u"].cpu().numpy()))
+            for a, b in zip(out[0][0], out[1][0]):
+                assert np.array_equal(a, b)
+            assert np.array_equal(out[0][1], out[1][1])
+            free = np.broadcast_to(mask == 0, (2, H, W)).reshape(-1)
+            assert (out[1][0][0] != 0)[free].mean() > 0.5
+    shapes = [(6, 40000), (300, 1024), (45, 70)]
+    fields = [wide, far, _field(45, 70, 47)]
+    zb = np.concatenate([f[1].ravel() for f in fields])
+    mb = np.concatenate([f[2].ravel() for f in fields])
+    res = []
+    for mode in (mpr.SWEEP_SPARSE, mpr.SWEEP_TILED):
+        ctx = mpr.Context(shapes=shapes, stream=torch.cuda.Stream(), seed=4, n_chains=2,
+                          precision=mpr.FP16, sweep_mode=mode)
+        ctx.batch_load(_dev(zb, torch.float64), _dev(mb, torch.uint8))
+        T = ctx.infer_temperature(16)
+        tr = [ctx.trace(i) for i in range(2 * len(shapes))]
+        ctx.run(4)
+        res.append((T, tr, ctx.predictions().cpu().numpy()))
+    assert np.array_equal(res[0][0], res[1][0])
+    for a, b in zip(res[0][1], res[1][1]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(res[0][2], res[1][2])
