@@ -832,6 +832,8 @@ struct mpr_ctx {
     GridInfo* d_gi = nullptr;
     void* d_state[2] = {nullptr, nullptr};
     double* d_acc = nullptr;     // compact FP64 accumulators: [gc][rank], gc's at its site_off
+    uint32_t* d_acc32 = nullptr; // FP16 storage: the compacted path's 32-bit sums since the last
+                                 // fold into d_acc (same layout; zero between library calls)
     uint64_t* d_rk_mask = nullptr;   // rank tables of the accumulators (acc_rank)
     int32_t* d_rk_base = nullptr;
     int32_t* d_rk_rows = nullptr;    // per grid and (y, c) row: totals, then their scan
@@ -942,14 +944,14 @@ static void free_device(mpr_ctx* c)
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
     void* ptrs[] = {c->d_gcs, c->d_items, c->d_ctl, c->d_run, c->d_dbg_run, c->d_gi,
-                    c->d_state[0], c->d_state[1], c->d_acc, c->d_zcopy, c->d_e_part,
+                    c->d_state[0], c->d_state[1], c->d_acc, c->d_acc32, c->d_zcopy, c->d_e_part,
                     c->d_a_part, c->d_trace, c->d_flag, c->d_ictl, c->d_gacc,
                     c->d_rk_mask, c->d_rk_base, c->d_rk_rows, c->d_rk_row_off};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     c->d_gcs = nullptr; c->d_items = nullptr; c->d_ctl = nullptr; c->d_run = nullptr;
     c->d_dbg_run = nullptr; c->d_gi = nullptr; c->d_state[0] = c->d_state[1] = nullptr;
-    c->d_acc = nullptr; c->d_zcopy = nullptr; c->d_e_part = nullptr; c->d_a_part = nullptr;
+    c->d_acc = nullptr; c->d_acc32 = nullptr; c->d_zcopy = nullptr; c->d_e_part = nullptr; c->d_a_part = nullptr;
     c->d_trace = nullptr; c->d_flag = nullptr; c->d_ictl = nullptr; c->d_gacc = nullptr;
     c->d_rk_mask = nullptr; c->d_rk_base = nullptr; c->d_rk_rows = nullptr; c->d_rk_row_off = nullptr;
     c->trace_cap = 0;
@@ -1156,6 +1158,7 @@ static int alloc_device(mpr_ctx* c)
     HIPCHK(c, hipMalloc(&c->d_gi, c->G * sizeof(GridInfo)));
     for (int b = 0; b < 2; ++b) HIPCHK(c, hipMalloc(&c->d_state[b], c->plane_elems * c->elem));
     HIPCHK(c, hipMalloc(&c->d_acc, c->chain_sites * sizeof(double)));
+    if (c->sprec == MPR_FP16) HIPCHK(c, hipMalloc(&c->d_acc32, c->chain_sites * sizeof(uint32_t)));
     HIPCHK(c, hipMalloc(&c->d_rk_mask, std::max<int64_t>(c->rk_entries, 1) * sizeof(uint64_t)));
     HIPCHK(c, hipMalloc(&c->d_rk_base, std::max<int64_t>(c->rk_entries, 1) * sizeof(int32_t)));
     HIPCHK(c, hipMalloc(&c->d_rk_rows, std::max<int64_t>(c->rk_rows, 1) * sizeof(int32_t)));
@@ -1620,6 +1623,7 @@ static int load_common(mpr_ctx* c, const double* z, const uint8_t* mask, bool fr
     HIPCHK(c, hipGetLastError());
     // compact accumulators: zeroed, and the rank tables of this data's prediction sites
     HIPCHK(c, hipMemsetAsync(c->d_acc, 0, c->chain_sites * sizeof(double), c->stream));
+    if (c->d_acc32) HIPCHK(c, hipMemsetAsync(c->d_acc32, 0, c->chain_sites * sizeof(uint32_t), c->stream));
     {
         int64_t max_e = 0, max_rows = 0;
         for (int g = 0; g < c->G; ++g) {
@@ -1788,6 +1792,7 @@ static void enqueue_sparse(mpr_ctx* c, int flags, int sweep_off, const RunCtl* r
         a.run = run;
         a.state = c->d_state[c->cur];
         a.acc = c->d_acc;
+        a.acc32 = c->d_acc32;
         a.rk_mask = c->d_rk_mask;
         a.rk_base = c->d_rk_base;
         a.dec = dec;
@@ -2149,6 +2154,21 @@ int mpr_burn_in(mpr_ctx* c, int32_t n)
     return run_sweeps(c, MODE_BURN, n);
 }
 
+// acc[i] += acc32[i] 2^-24, acc32[i] = 0: exact (both are whole multiples of 2^-24 far below
+// 2^29), so the FP64 sums equal those of adding each sweep's FP16 value in double precision
+__global__ __launch_bounds__(256) void k_acc_fold(double* acc, uint32_t* acc32, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = acc32[i];
+        acc[i] += (double)v * 0x1p-24;
+        acc32[i] = 0u;
+    }
+}
+
+// the compacted path's FP16 averaging sweeps sum into 32-bit words: at most 2^24 units per sweep
+// (a value of 1), so 128 sweeps stay below 2^31
+constexpr int kAcc32Sweeps = 128;
+
 int mpr_run(mpr_ctx* c, int32_t n_avg)
 {
     int rc = usable(c);
@@ -2156,7 +2176,18 @@ int mpr_run(mpr_ctx* c, int32_t n_avg)
     if (n_avg < 0) return fail(c, MPR_EINVAL, "n_avg < 0");
     if (c->phase < PH_TEMPERED) return fail(c, MPR_ESTATE, "no temperature: infer or set it first");
     rc = mark(c, PHASE_RUN, 0);
-    if (!rc) rc = run_sweeps(c, MODE_AVG, n_avg);
+    if (c->sparse && c->d_acc32) {
+        const unsigned blocks = (unsigned)std::min<int64_t>(4096, (c->chain_sites + 255) / 256);
+        for (int64_t done = 0; !rc && done < n_avg; done += kAcc32Sweeps) {
+            rc = run_sweeps(c, MODE_AVG, (int)std::min<int64_t>(kAcc32Sweeps, n_avg - done));
+            if (rc) return rc;
+            hipLaunchKernelGGL(k_acc_fold, dim3(std::max(blocks, 1u)), dim3(256), 0, c->stream, c->d_acc, c->d_acc32,
+                               c->chain_sites);
+            HIPCHK(c, hipGetLastError());
+        }
+    } else if (!rc) {
+        rc = run_sweeps(c, MODE_AVG, n_avg);
+    }
     if (!rc) rc = mark(c, PHASE_RUN, 1, n_avg);
     if (rc) return rc;
     c->n_avg += n_avg;

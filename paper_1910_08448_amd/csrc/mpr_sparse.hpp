@@ -18,6 +18,8 @@
 // started with).
 #pragma once
 
+#include <type_traits>
+
 #include "mpr_device.hpp"
 
 namespace mpr {
@@ -35,6 +37,7 @@ struct SparseArgs {
     const RunCtl* run;
     void* state;               // state planes, updated in place
     double* acc;
+    uint32_t* acc32;           // FP16 storage: running sums in units of 2^-24 since the last fold
     const uint64_t* rk_mask;   // rank tables of the compact accumulators (see acc_rank)
     const int32_t* rk_base;
     uint8_t* dec;
@@ -92,6 +95,10 @@ __global__ __launch_bounds__(256) void k_sparse(SparseArgs a)
     using Raw = typename St::raw;
     constexpr uint32_t kRaw = (uint32_t)sizeof(Raw);
     constexpr bool FUSED = (FLAGS & F_ENERGY) != 0;   // this path sums energies in double precision
+    // FP16 storage: every stored angle is a whole number of 2^-24 units in [0, 1], so averaging
+    // sweeps add them exactly into 32-bit sums (at most 128 sweeps between two folds into the
+    // FP64 sums), which equal the FP64 running sums bit for bit, in half their bytes
+    constexpr bool ACC32 = std::is_same_v<S, _Float16>;
     const int lane = threadIdx.x & (kWave - 1);
     const int lblock = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int wid = __builtin_amdgcn_readfirstlane(lblock * kWavesPerBlock + (int)(threadIdx.x >> 6));
@@ -130,7 +137,8 @@ __global__ __launch_bounds__(256) void k_sparse(SparseArgs a)
     const int plane_sz = H * pitch;
     const int oc = (1 - C) * plane_sz;
     const Rsrc rs = make_rsrc((Raw*)a.state + g.plane_off, 2u * (uint32_t)plane_sz * kRaw);
-    const Rsrc ra = make_rsrc(a.acc + g.site_off, (uint32_t)(H * W) * 8u);
+    const Rsrc ra = ACC32 ? make_rsrc(a.acc32 + g.site_off, (uint32_t)(H * W) * 4u)
+                          : make_rsrc(a.acc + g.site_off, (uint32_t)(H * W) * 8u);
 
     // one listed site: its entry, position, which neighbours exist, the stored values of the
     // site and of its four neighbours in the other plane (column = grid x >> 1), and (averaging
@@ -182,10 +190,12 @@ __global__ __launch_bounds__(256) void k_sparse(SparseArgs a)
         // hides it (a scheduling barrier keeps it there)
         uint32_t ao = kBufOOB;
         double sum = 0.0;
+        uint32_t sum32 = 0;
         if constexpr ((FLAGS & F_ACC) != 0) {
             const int64_t rank = (int64_t)t.rkb + (int64_t)__popcll(t.rkm & ((1ull << (t.k & 63)) - 1ull));
-            ao = is_free ? (uint32_t)rank * 8u : kBufOOB;
-            sum = buf_load_f64(ra, ao);
+            ao = is_free ? (uint32_t)rank * (ACC32 ? 4u : 8u) : kBufOOB;
+            if constexpr (ACC32) sum32 = __builtin_amdgcn_raw_buffer_load_b32(ra, (int)ao, 0, 0);
+            else sum = buf_load_f64(ra, ao);
             __builtin_amdgcn_sched_barrier(0);
         }
         F sl, cl, sr, cr, su, cu, sd, cd;
@@ -226,7 +236,13 @@ __global__ __launch_bounds__(256) void k_sparse(SparseArgs a)
             e_hi += f.hi;
             e_lo += f.lo;
         }
-        if constexpr ((FLAGS & F_ACC) != 0) buf_store_f64(ra, ao, sum + St::template value<double>(nv));
+        if constexpr ((FLAGS & F_ACC) != 0) {
+            if constexpr (ACC32)
+                __builtin_amdgcn_raw_buffer_store_b32(sum32 + (uint32_t)(St::template value<float>(nv) * 16777216.0f),
+                                                      ra, (int)ao, 0, 0);
+            else
+                buf_store_f64(ra, ao, sum + St::template value<double>(nv));
+        }
         if ((FLAGS & F_DEC) && is_free) a.dec[g.site_off + (int64_t)t.y * W + t.x] = (uint8_t)o.dec;
     };
 
