@@ -832,7 +832,7 @@ struct mpr_ctx {
     GridInfo* d_gi = nullptr;
     void* d_state[2] = {nullptr, nullptr};
     double* d_acc = nullptr;     // compact FP64 accumulators: [gc][rank], gc's at its site_off
-    uint32_t* d_acc32 = nullptr; // FP16 storage: the compacted path's 32-bit sums since the last
+    uint32_t* d_acc32 = nullptr; // FP16 storage: 32-bit sums of the averaging sweeps since the last
                                  // fold into d_acc (same layout; zero between library calls)
     uint64_t* d_rk_mask = nullptr;   // rank tables of the accumulators (acc_rank)
     int32_t* d_rk_base = nullptr;
@@ -1740,6 +1740,7 @@ static void enqueue_tiled(mpr_ctx* c, int flags, int sweep_off, int src_buf, con
     a.src = c->d_state[src_buf];
     a.dst = c->d_state[1 - src_buf];
     a.acc = c->d_acc;
+    a.acc32 = c->d_acc32;
     a.rk_mask = c->d_rk_mask;
     a.rk_base = c->d_rk_base;
     a.dec = dec;
@@ -1842,6 +1843,7 @@ static void enqueue_sweep(mpr_ctx* c, int flags, int sweep_off, int src_buf, con
     a.src = c->d_state[src_buf];
     a.dst = c->d_state[1 - src_buf];
     a.acc = c->d_acc;
+    a.acc32 = c->d_acc32;
     a.rk_mask = c->d_rk_mask;
     a.rk_base = c->d_rk_base;
     a.dec = dec;
@@ -2165,8 +2167,8 @@ __global__ __launch_bounds__(256) void k_acc_fold(double* acc, uint32_t* acc32, 
     }
 }
 
-// the compacted path's FP16 averaging sweeps sum into 32-bit words: at most 2^24 units per sweep
-// (a value of 1), so 128 sweeps stay below 2^31
+// FP16 averaging sweeps sum into 32-bit words (kAcc32): at most 2^24 units per sweep (a value
+// of 1), so 128 sweeps stay below 2^31
 constexpr int kAcc32Sweeps = 128;
 
 int mpr_run(mpr_ctx* c, int32_t n_avg)
@@ -2176,7 +2178,7 @@ int mpr_run(mpr_ctx* c, int32_t n_avg)
     if (n_avg < 0) return fail(c, MPR_EINVAL, "n_avg < 0");
     if (c->phase < PH_TEMPERED) return fail(c, MPR_ESTATE, "no temperature: infer or set it first");
     rc = mark(c, PHASE_RUN, 0);
-    if (c->sparse && c->d_acc32) {
+    if (c->d_acc32) {
         const unsigned blocks = (unsigned)std::min<int64_t>(4096, (c->chain_sites + 255) / 256);
         for (int64_t done = 0; !rc && done < n_avg; done += kAcc32Sweeps) {
             rc = run_sweeps(c, MODE_AVG, (int)std::min<int64_t>(kAcc32Sweeps, n_avg - done));

@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace mpr {
 
 // ------------------------------------------------------------------ shared host/device types
@@ -98,6 +100,7 @@ struct SweepArgs {
     const void* src;
     void* dst;
     double* acc;
+    uint32_t* acc32;           // FP16 storage: running sums in units of 2^-24 (see kAcc32)
     const uint64_t* rk_mask;   // rank tables of the compact accumulators (see acc_rank)
     const int32_t* rk_base;
     uint8_t* dec;
@@ -266,6 +269,18 @@ template <> struct Store<_Float16> {
     }
     template <class F> static __device__ __forceinline__ F round(F u) { return (F)(float)(_Float16)(float)u; }
 };
+
+// Averaging sweeps with FP16 storage sum into 32-bit words: every FP16 value in [0, 1] is a
+// whole number of 2^-24 units (at most 2^24), so the words hold exact sums, which the host folds
+// into the FP64 running sums after at most 128 sweeps (below 2^31).  Each partial sum of adding
+// the values in double precision is a multiple of 2^-24 far below 2^29, exact as well: both
+// give the same sums bit for bit, the words in half the bytes.  (16-bit fixed point,
+// u = k / 32767, is not a dyadic fraction and keeps the FP64 sums.)
+template <class S> constexpr bool kAcc32 = std::is_same_v<S, _Float16>;
+template <class S> __device__ __forceinline__ uint32_t acc_units(typename Store<S>::raw r)
+{
+    return (uint32_t)(Store<S>::template value<float>(r) * 16777216.0f);
+}
 
 // 16-bit fixed point: 15 fraction bits with u = k / 32767 (uniform resolution 3.1e-5 of a turn,
 // against FP16's 2^-11 just below 1) and the sample flag in bit 15.
@@ -828,9 +843,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(F) 
     // (2 jj is even, so both share a mask block); lanes without output look up column 0 (halo
     // lanes' columns may lie outside the grid).  Measured: 100 averaging sweeps of the 256-grid
     // batch 177.6 -> 161.8 ms in FP32, 168.6 -> 140.4 ms in FP16.
-    struct AccRow { uint32_t oa, ob; double sa, sb; };
+    using AccSum = std::conditional_t<kAcc32<S>, uint32_t, double>;
+    constexpr uint32_t kAccBytes = kAcc32<S> ? 4u : 8u;
+    struct AccRow { uint32_t oa, ob; AccSum sa, sb; };
     struct RkRow { uint64_t m; int32_t b; };
-    const Rsrc ra = make_rsrc(a.acc + g.site_off, (uint32_t)(it.H * it.W) * 8u);
+    const Rsrc ra = kAcc32<S> ? make_rsrc(a.acc32 + g.site_off, (uint32_t)(it.H * it.W) * 4u)
+                              : make_rsrc(a.acc + g.site_off, (uint32_t)(it.H * it.W) * 8u);
     const int ck = out_lane ? col : 0;
     const uint64_t below = (1ull << (ck & 63)) - 1ull;
     // rank-table words of row y (clamped into the grid: rows outside it are never stored)
@@ -845,15 +863,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(F) 
         const bool fb = on & exists(y, par, 1) & !St::sample(old.b);
         const int64_t kr = (int64_t)rk.b + (int64_t)__popcll(rk.m & below);
         AccRow r;
-        r.oa = fa ? (uint32_t)kr * 8u : kBufOOB;
-        r.ob = fb ? (uint32_t)(kr + fa) * 8u : kBufOOB;
-        r.sa = buf_load_f64(ra, r.oa);
-        r.sb = buf_load_f64(ra, r.ob);
+        r.oa = fa ? (uint32_t)kr * kAccBytes : kBufOOB;
+        r.ob = fb ? (uint32_t)(kr + fa) * kAccBytes : kBufOOB;
+        if constexpr (kAcc32<S>) {
+            r.sa = __builtin_amdgcn_raw_buffer_load_b32(ra, (int)r.oa, 0, 0);
+            r.sb = __builtin_amdgcn_raw_buffer_load_b32(ra, (int)r.ob, 0, 0);
+        } else {
+            r.sa = buf_load_f64(ra, r.oa);
+            r.sb = buf_load_f64(ra, r.ob);
+        }
         return r;
     };
     auto acc_store = [&](const AccRow& r, const Pair& nv) __attribute__((always_inline)) {
-        buf_store_f64(ra, r.oa, r.sa + St::template value<double>(nv.a));
-        buf_store_f64(ra, r.ob, r.sb + St::template value<double>(nv.b));
+        if constexpr (kAcc32<S>) {
+            __builtin_amdgcn_raw_buffer_store_b32(r.sa + acc_units<S>(nv.a), ra, (int)r.oa, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(r.sb + acc_units<S>(nv.b), ra, (int)r.ob, 0, 0);
+        } else {
+            buf_store_f64(ra, r.oa, r.sa + St::template value<double>(nv.a));
+            buf_store_f64(ra, r.ob, r.sb + St::template value<double>(nv.b));
+        }
     };
 
     // Skewed pipeline: iteration k updates colour 0 at row k and colour 1 at row k - 2.  The two

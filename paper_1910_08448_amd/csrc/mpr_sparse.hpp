@@ -18,8 +18,6 @@
 // started with).
 #pragma once
 
-#include <type_traits>
-
 #include "mpr_device.hpp"
 
 namespace mpr {
@@ -37,7 +35,7 @@ struct SparseArgs {
     const RunCtl* run;
     void* state;               // state planes, updated in place
     double* acc;
-    uint32_t* acc32;           // FP16 storage: running sums in units of 2^-24 since the last fold
+    uint32_t* acc32;           // FP16 storage: running sums in units of 2^-24 (see kAcc32)
     const uint64_t* rk_mask;   // rank tables of the compact accumulators (see acc_rank)
     const int32_t* rk_base;
     uint8_t* dec;
@@ -95,10 +93,7 @@ __global__ __launch_bounds__(256) void k_sparse(SparseArgs a)
     using Raw = typename St::raw;
     constexpr uint32_t kRaw = (uint32_t)sizeof(Raw);
     constexpr bool FUSED = (FLAGS & F_ENERGY) != 0;   // this path sums energies in double precision
-    // FP16 storage: every stored angle is a whole number of 2^-24 units in [0, 1], so averaging
-    // sweeps add them exactly into 32-bit sums (at most 128 sweeps between two folds into the
-    // FP64 sums), which equal the FP64 running sums bit for bit, in half their bytes
-    constexpr bool ACC32 = std::is_same_v<S, _Float16>;
+    constexpr bool ACC32 = kAcc32<S>;              // FP16 storage: 32-bit running sums
     const int lane = threadIdx.x & (kWave - 1);
     const int lblock = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int wid = __builtin_amdgcn_readfirstlane(lblock * kWavesPerBlock + (int)(threadIdx.x >> 6));
@@ -238,8 +233,7 @@ __global__ __launch_bounds__(256) void k_sparse(SparseArgs a)
         }
         if constexpr ((FLAGS & F_ACC) != 0) {
             if constexpr (ACC32)
-                __builtin_amdgcn_raw_buffer_store_b32(sum32 + (uint32_t)(St::template value<float>(nv) * 16777216.0f),
-                                                      ra, (int)ao, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b32(sum32 + acc_units<S>(nv), ra, (int)ao, 0, 0);
             else
                 buf_store_f64(ra, ao, sum + St::template value<double>(nv));
         }

@@ -60,6 +60,7 @@ struct TiledArgs {
     const void* src;
     void* dst;
     double* acc;
+    uint32_t* acc32;           // FP16 storage: running sums in units of 2^-24 (see kAcc32)
     const uint64_t* rk_mask;   // rank tables of the compact accumulators (see acc_rank)
     const int32_t* rk_base;
     uint8_t* dec;
@@ -294,10 +295,18 @@ __global__ __launch_bounds__(NW * kWave) void k_tiled(TiledArgs a)
 
     int n_acc = 0;
     int64_t e_hi = 0, e_lo = 0;
-    const Rsrc ra = make_rsrc(a.acc + g.site_off, (uint32_t)(H * W) * 8u);
+    const Rsrc ra = kAcc32<S> ? make_rsrc(a.acc32 + g.site_off, (uint32_t)(H * W) * 4u)
+                              : make_rsrc(a.acc + g.site_off, (uint32_t)(H * W) * 8u);
     auto accumulate = [&](int c, int yy, int kk, Raw nv) {
-        const uint32_t ao = (uint32_t)acc_rank(a.rk_mask, a.rk_base, g.rk_off, pitch, c, yy, kk) * 8u;
-        buf_store_f64(ra, ao, buf_load_f64(ra, ao) + St::template value<double>(nv));
+        const uint32_t rank = (uint32_t)acc_rank(a.rk_mask, a.rk_base, g.rk_off, pitch, c, yy, kk);
+        if constexpr (kAcc32<S>) {
+            const uint32_t ao = rank * 4u;
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_amdgcn_raw_buffer_load_b32(ra, (int)ao, 0, 0) + acc_units<S>(nv),
+                                                  ra, (int)ao, 0, 0);
+        } else {
+            const uint32_t ao = rank * 8u;
+            buf_store_f64(ra, ao, buf_load_f64(ra, ao) + St::template value<double>(nv));
+        }
     };
 
     // colour 0: the tile and its ring, from the old colour-1 stage

@@ -965,29 +965,42 @@ def test_sparse_far_rows_and_wide_grids(mpr):
     assert np.array_equal(res[0][2], res[1][2])
 
 
-@pytest.mark.parametrize("boundary", [0, 1])
-def test_fp16_compacted_running_sums_over_many_sweeps(mpr, boundary):
-    """With FP16 storage the compacted path sums its averaging sweeps in 32-bit words of 2^-24
-    units and folds them into the FP64 sums at least every 128 sweeps: runs of 130 and then 3
-    averaging sweeps (two folds in one call, then another call) give running sums and
-    predictions bit for bit equal to the tiled path's, which adds each sweep in double
-    precision; a batch of uneven grids, two chains."""
-    shapes = [(45, 70), (17, 300), (64, 64)] if boundary == 0 else [(16, 24), (34, 264)]
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_fp16_running_sums_over_many_sweeps(mpr, mode):
+    """With FP16 storage the averaging sweeps sum into 32-bit words of 2^-24 units, folded into
+    the FP64 sums after at most 128 sweeps.  On every sweep path, the running sums after runs of
+    130 and then 3 averaging sweeps (two folds in one call, then another call) equal bit for bit
+    the double-precision sum of the angles read back after each of 133 one-sweep runs of a
+    second context, and the two contexts' sums and predictions are equal; a batch of uneven open
+    grids with two chains."""
+    shapes = [(45, 70), (17, 300), (64, 64)]
+    chains = 2
     fields = [_field(h, w, 900 + i) for i, (h, w) in enumerate(shapes)]
     z = np.concatenate([f[1].ravel() for f in fields])
     m = np.concatenate([f[2].ravel() for f in fields])
-    res = []
-    for mode in (mpr.SWEEP_SPARSE, mpr.SWEEP_TILED):
-        ctx = mpr.Context(shapes=shapes, stream=torch.cuda.Stream(), seed=6, n_chains=2,
-                          precision=mpr.FP16, boundary=boundary, sweep_mode=mode)
+    # state layout: grid, then chain, then the grid's sites row-major
+    free = np.concatenate([np.tile((f[2] == 0).ravel(), chains) for f in fields])
+
+    def tempered():
+        ctx = mpr.Context(shapes=shapes, stream=torch.cuda.Stream(), seed=6, n_chains=chains,
+                          precision=mpr.FP16, sweep_mode=mode)
         ctx.batch_load(_dev(z, torch.float64), _dev(m, torch.uint8))
         assert ctx.sweep_mode() == mode
         ctx.infer_temperature(12)
-        ctx.run(130)
-        st1 = ctx.get_state()["acc"].cpu().numpy()
-        ctx.run(3)
-        st2 = ctx.get_state()
-        res.append((st1, st2["acc"].cpu().numpy(), st2["u"].cpu().numpy(), ctx.predictions().cpu().numpy()))
-    for a, b in zip(res[0], res[1]):
-        assert np.array_equal(a, b)
-    assert res[0][1].max() > 20.0 and (res[0][1] > res[0][0]).any()
+        return ctx
+
+    a = tempered()
+    a.run(130)
+    acc130 = a.get_state()["acc"].cpu().numpy()
+    a.run(3)
+    acc_a = a.get_state()["acc"].cpu().numpy()
+    b = tempered()
+    host = np.zeros_like(acc_a)
+    for _ in range(133):
+        b.run(1)
+        host += b.get_state()["u"].cpu().numpy()
+    acc_b = b.get_state()["acc"].cpu().numpy()
+    assert np.array_equal(acc_a[free], host[free])
+    assert np.array_equal(acc_a, acc_b)
+    assert np.array_equal(a.predictions().cpu().numpy(), b.predictions().cpu().numpy())
+    assert acc_a[free].max() > 20.0 and (acc_a[free] > acc130[free]).any()
